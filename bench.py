@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of voxel-driven FDK back-projection on one MI355X.
+
+Workload (default): 512^3 volume (1 mm voxels), 1024 views over 360 degrees,
+1024 x 1024 detector (1 mm), SOD 750 mm, SDD 1200 mm; filtered projections of a
+seeded 40-ellipsoid phantom generated on the GPU (analytic line integrals +
+FDK ramp filter), volume zero-initialised.
+
+One step = zero the volume, FP16 storage pre-pass (per-view scale + binary16
+codes), back-projection of all views with FP32 coordinates and accumulation.
+The FP32-storage step (zero + back-projection of the float32 stack) is timed
+the same way and reported beside it.  GUPS = nx ny nz np / t / 1e9.
+
+Prints ONE JSON line.  Also reports the dominant kernel against its roofline
+(timed with HIP events on the stream it runs on) and the FP64 oracle timed on
+the host's cores on a bounded sub-block of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU lane-operations per voxel update in the hoisted method, FP32, no packed
+# math: v = v0 + k dv (1), fraction and row of v (2), two horizontal lerps
+# (2 + 2), one vertical lerp (2), weighted accumulation (1).
+OPS_PER_UPDATE = 10
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = issue rate of non-packed
+# FP32 VALU lane-operations.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench %s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, mats, seconds: float):
+    """The FP64 oracle on a centred sub-block of the same workload."""
+    import numpy as np
+    import oracle
+    import workloads as wl
+    nz, ny, nx = cfg["shape"]
+    npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
+    log("cpu baseline: host stack", (npv, nh, nw))
+    proj = wl.gaussian(cfg["seed"] + 999, (npv, nh, nw))
+    threads = oracle.max_threads()
+
+    def run(b):
+        k0, j0, i0 = nz // 2 - b // 2, ny // 2 - b // 2, nx // 2 - b // 2
+        t = time.perf_counter()
+        oracle.backproject_block(proj, mats, cfg["shape"], cfg["voxel"],
+                                 ((k0, k0 + b), (j0, j0 + b), (i0, i0 + b)))
+        return time.perf_counter() - t
+
+    b = 8
+    dt = run(b)
+    while dt < 0.5 and b < 64:
+        b *= 2
+        dt = run(b)
+    rate = b ** 3 * npv / dt
+    b2 = int(round((seconds * rate / npv) ** (1.0 / 3.0)))
+    b2 = max(8, min(b2, min(nx, ny, nz)))
+    dt = run(b2)
+    gups = b2 ** 3 * npv / dt / 1e9
+    log("cpu baseline: %d^3 block x %d views in %.2fs, %d threads" % (b2, npv, dt, threads))
+    return {"value": gups, "unit": "GUPS", "cores": threads, "kind": "oracle",
+            "sample": "centred %d^3 sub-block of the %dx%dx%d volume, all %d views, "
+                      "Gaussian projections of the same shape; %.1f s" % (b2, nx, ny, nz, npv, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the back-projector has no multi-GPU path in this "
+              "build (a z-slab split needs no exchange; see the design notes). Use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import workloads as wl
+    import paper_2104_13248_amd as fdk
+
+    cfg = wl.CONFIGS[args.config]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nz, ny, nx = cfg["shape"]
+    npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
+    scan = cfg["scan"]
+    mats = fdk.scan_matrices(scan, npv, nh, nw)
+    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], npv, nh, nw, mats)
+    log("config", args.config, cfg["shape"], (npv, nh, nw), "plan", plan)
+
+    # ---- synthetic input, generated on the GPU (not timed)
+    ell = wl.config_ellipsoids(cfg, 0)
+    filt = torch.empty((npv, nh, nw), dtype=torch.float32, device=dev)
+    chunk = 128
+    raw = torch.empty((chunk, nh, nw), dtype=torch.float32, device=dev)
+    for v0 in range(0, npv, chunk):
+        n = min(chunk, npv - v0)
+        raw[:n].zero_()
+        fdk.phantom_project(ell, scan, raw[:n], view_begin=v0, np_total=npv)
+        fdk.fdk_filter(raw[:n], scan, np_total=npv, out=filt[v0:v0 + n])
+    del raw
+    torch.cuda.synchronize()
+    log("input ready: filtered stack %.2f GiB" % (filt.numel() * 4 / 2**30))
+
+    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    n_upd = nx * ny * nz * npv
+
+    def step_f16(events=None):
+        vol.zero_()
+        h, s = fdk.quantize_f16(filt)
+        if events is not None:
+            events[0].record(stream)
+        fdk.backproject(vol, h, mats, cfg["voxel"], scale=s)
+        if events is not None:
+            events[1].record(stream)
+
+    def step_f32(events=None):
+        vol.zero_()
+        if events is not None:
+            events[0].record(stream)
+        fdk.backproject(vol, filt, mats, cfg["voxel"])
+        if events is not None:
+            events[1].record(stream)
+
+    results = {}
+    for name, step in (("f32", step_f32), ("f16", step_f16)):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(args.steps):
+            step(ev[q])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        ms = (t1 - t0) * 1e3 / args.steps
+        results[name] = dict(ms_per_step=ms, kernel_ms=k_ms, gups=n_upd / (ms * 1e-3) / 1e9,
+                             kernel_gups=n_upd / (k_ms * 1e-3) / 1e9)
+        log(name, results[name])
+        print("progress: %s timed" % name, file=sys.stderr, flush=True)
+
+    f16 = results["f16"]
+    f32 = results["f32"]
+    k_s = f16["kernel_ms"] * 1e-3
+    achieved = n_upd * OPS_PER_UPDATE / k_s / 1e12
+    vol_bytes = nx * ny * nz * 4
+    hbm_alg = 2 * vol_bytes + npv * nh * nw * 2 + npv * 4           # volume RMW + f16 stack
+    out = {
+        "metric": "GUPS (giga voxel-updates/s) FDK backproject, FP16-store vs FP32 at rel-L2<=1e-3",
+        "value": f16["gups"],
+        "unit": "GUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f16["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: GPU analytic line integrals of a seeded 40-ellipsoid phantom, "
+                "FDK ramp-filtered; FP16 storage with per-view scale",
+        "config": {"workload": "fdk_backprojection_%dx%dx%d_%dviews_%dx%d" % (nx, ny, nz, npv, nh, nw),
+                   "volume": [nz, ny, nx], "voxel_mm": list(cfg["voxel"]), "views": npv,
+                   "detector": [nh, nw], "pixel_mm": [scan["du"], scan["dv"]],
+                   "sod_mm": scan["sod"], "sdd_mm": scan["sdd"], "storage": "f16",
+                   "tile": [plan["tile_x"], plan["tile_y"], plan["kz"]],
+                   "lds_bytes": plan["lds_bytes"]},
+        "fp32_storage": {"value": f32["gups"], "unit": "GUPS", "ms_per_step": f32["ms_per_step"],
+                         "kernel_ms": f32["kernel_ms"]},
+        "f16_over_f32": f16["gups"] / f32["gups"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "bp_kernel", "kernel_ms": f16["kernel_ms"],
+                     "ops_per_update": OPS_PER_UPDATE,
+                     "hbm_algorithmic_gbs": hbm_alg / k_s / 1e9,
+                     "hbm_frac": hbm_alg / k_s / 1e9 / HBM_PEAK_GBS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, np.asarray(mats), args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

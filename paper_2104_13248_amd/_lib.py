@@ -1,0 +1,101 @@
+"""ctypes binding of libfdk.so (include/fdk.h): argument marshalling only.
+
+Every operation runs in the HIP kernels of the library; this module checks
+tensor placement, dtype and contiguity, passes raw device pointers and the
+current HIP stream, and turns status codes into ``FdkError``.  There is no
+fallback: if the library is missing, importing the package fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfdk.so")
+
+FDK_F32 = 0
+FDK_F16 = 1
+
+
+class FdkError(RuntimeError):
+    """Non-OK status from the library; ``code`` is the fdk_status value."""
+
+    def __init__(self, code: int, message: str):
+        super().__init__("fdk status %d: %s" % (code, message))
+        self.code = code
+
+
+class Volume(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("cz", ctypes.c_double)]
+
+
+class Stack(ctypes.Structure):
+    _fields_ = [("np", ctypes.c_int32), ("nh", ctypes.c_int32), ("nw", ctypes.c_int32),
+                ("dtype", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libfdk.so not built: run `python -m paper_2104_13248_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int32
+    D = ctypes.c_double
+    VP = ctypes.POINTER(Volume)
+    SP = ctypes.POINTER(Stack)
+    sigs = {
+        "fdk_backproject": [VP, P, SP, P, P, P, P],
+        "fdk_backproject_slab": [VP, I, I, P, SP, P, P, P, P],
+        "fdk_forwardproject": [VP, P, SP, P, P, P],
+        "fdk_filter": [SP, P, P, D, D, D, D, D, D, D, I, P],
+        "fdk_quantize_f16": [I, I, I, P, P, P, P],
+        "fdk_circular_matrices": [I, D, D, D, D, I, I, D, D, D, D, P],
+        "fdk_phantom_project": [P, I, SP, P, D, D, D, D, D, D, D, D, I, I, P],
+        "fdk_bp_plan": [VP, SP, P, P],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.fdk_last_error.restype = ctypes.c_char_p
+    lib.fdk_last_error.argtypes = []
+    lib.fdk_status_string.restype = ctypes.c_char_p
+    lib.fdk_status_string.argtypes = [ctypes.c_int]
+    return lib
+
+
+lib = _load()
+
+#: names declared in include/fdk.h
+EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_forwardproject", "fdk_filter",
+           "fdk_quantize_f16", "fdk_circular_matrices", "fdk_phantom_project", "fdk_bp_plan",
+           "fdk_last_error", "fdk_status_string")
+
+
+def check(code: int) -> None:
+    if code != 0:
+        msg = lib.fdk_last_error().decode() or lib.fdk_status_string(code).decode()
+        raise FdkError(code, msg)
+
+
+def volume_struct(shape, voxel, centre=(0.0, 0.0, 0.0)) -> Volume:
+    nz, ny, nx = (int(n) for n in shape)
+    return Volume(nx, ny, nz, float(voxel[0]), float(voxel[1]), float(voxel[2]),
+                  float(centre[0]), float(centre[1]), float(centre[2]))
+
+
+def stack_struct(np_views, nh, nw, dtype=FDK_F32) -> Stack:
+    return Stack(int(np_views), int(nh), int(nw), int(dtype))
+
+
+def host_f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)

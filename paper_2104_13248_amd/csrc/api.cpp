@@ -1,0 +1,233 @@
+// extern "C" entry points of include/fdk.h: argument validation (host, before
+// any HIP call), FP64 geometry checks, scratch management and kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace fdk;
+
+namespace {
+
+fdk_status common_checks(const fdk_volume* vg, const fdk_stack* sg, bool allow_f16,
+                         const double* mats, std::vector<IndexMatrix>* M)
+{
+    fdk_status s = validate_volume(vg);
+    if (s != FDK_OK) return s;
+    s = validate_stack(sg, allow_f16);
+    if (s != FDK_OK) return s;
+    return validate_geometry(*vg, *sg, mats, M);
+}
+
+void fill_grid(const fdk_volume& vg, double& ox, double& oy, double& oz)
+{
+    ox = vg.cx - 0.5 * (vg.nx - 1) * vg.dx;
+    oy = vg.cy - 0.5 * (vg.ny - 1) * vg.dy;
+    oz = vg.cz - 0.5 * (vg.nz - 1) * vg.dz;
+}
+
+}  // namespace
+
+extern "C" fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, const double* mats,
+                                  int64_t* out)
+{
+    if (!out) return fail(FDK_E_INVALID, "output array is NULL");
+    std::vector<IndexMatrix> M;
+    fdk_status s = common_checks(vg, sg, true, mats, &M);
+    if (s != FDK_OK) return s;
+    BpPlan plan;
+    s = make_bp_plan(*vg, *sg, M, plan);
+    if (s != FDK_OK) return s;
+    out[0] = kTile;
+    out[1] = kTile;
+    out[2] = plan.kz;
+    out[3] = plan.pitch;
+    out[4] = plan.rows;
+    out[5] = plan.lds_bytes;
+    out[6] = plan.blocks;
+    out[7] = kThreads;
+    return FDK_OK;
+}
+
+extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k_count,
+                                           float* vol_slab, const fdk_stack* sg, const void* proj,
+                                           const float* scale, const double* mats, void* stream)
+{
+    std::vector<IndexMatrix> M;
+    fdk_status s = common_checks(vg, sg, true, mats, &M);
+    if (s != FDK_OK) return s;
+    if (!vol_slab) return fail(FDK_E_INVALID, "volume pointer is NULL");
+    if (!proj) return fail(FDK_E_INVALID, "projection pointer is NULL");
+    if (sg->dtype == FDK_F16 && !scale)
+        return fail(FDK_E_INVALID, "binary16 projections need a per-view scale array");
+    if (sg->dtype == FDK_F32 && scale)
+        return fail(FDK_E_INVALID, "a scale array is only accepted with binary16 projections");
+    if (k_begin < 0 || k_count <= 0 || (int64_t)k_begin + k_count > vg->nz)
+        return fail(FDK_E_INVALID, "slab [k_begin, k_begin + k_count) outside the volume");
+    BpPlan plan;
+    s = make_bp_plan(*vg, *sg, M, plan);
+    if (s != FDK_OK) return s;
+
+    const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
+    void* d_world = nullptr;
+    void* d_index = nullptr;
+    s = upload_async(mats, mbytes, stream, &d_world);
+    if (s != FDK_OK) return s;
+    s = device_alloc_async(mbytes, stream, &d_index);
+    if (s != FDK_OK) {
+        device_free_async(d_world, stream);
+        return s;
+    }
+    BpLaunch a;
+    a.proj = proj;
+    a.scale = scale;
+    a.mats_world = (const double*)d_world;
+    a.mats_index = (double*)d_index;
+    a.vol = vol_slab;
+    a.nx = vg->nx; a.ny = vg->ny; a.nz = vg->nz;
+    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+    a.k_begin = k_begin;
+    a.k_end = k_begin + k_count;
+    a.dx = vg->dx; a.dy = vg->dy; a.dz = vg->dz;
+    fill_grid(*vg, a.ox, a.oy, a.oz);
+    a.f16 = sg->dtype == FDK_F16;
+    s = launch_backproject(a, plan, stream);
+    fdk_status s2 = device_free_async(d_index, stream);
+    fdk_status s3 = device_free_async(d_world, stream);
+    if (s != FDK_OK) return s;
+    return s2 != FDK_OK ? s2 : s3;
+}
+
+extern "C" fdk_status fdk_backproject(const fdk_volume* vg, float* vol, const fdk_stack* sg,
+                                      const void* proj, const float* scale, const double* mats,
+                                      void* stream)
+{
+    fdk_status s = validate_volume(vg);
+    if (s != FDK_OK) return s;
+    return fdk_backproject_slab(vg, 0, vg->nz, vol, sg, proj, scale, mats, stream);
+}
+
+extern "C" fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
+                                         const fdk_stack* sg, float* proj, const double* mats,
+                                         void* stream)
+{
+    std::vector<IndexMatrix> M;
+    fdk_status s = common_checks(vg, sg, false, mats, &M);
+    if (s != FDK_OK) return s;
+    if (!vol) return fail(FDK_E_INVALID, "volume pointer is NULL");
+    if (!proj) return fail(FDK_E_INVALID, "projection pointer is NULL");
+    BpPlan plan;
+    s = make_bp_plan(*vg, *sg, M, plan);
+    if (s != FDK_OK) return s;
+    const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
+    void* d_world = nullptr;
+    void* d_index = nullptr;
+    s = upload_async(mats, mbytes, stream, &d_world);
+    if (s != FDK_OK) return s;
+    s = device_alloc_async(mbytes, stream, &d_index);
+    if (s != FDK_OK) {
+        device_free_async(d_world, stream);
+        return s;
+    }
+    FpLaunch a;
+    a.vol = vol;
+    a.proj = proj;
+    a.mats_world = (const double*)d_world;
+    a.mats_index = (double*)d_index;
+    a.nx = vg->nx; a.ny = vg->ny; a.nz = vg->nz;
+    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+    a.dx = vg->dx; a.dy = vg->dy; a.dz = vg->dz;
+    fill_grid(*vg, a.ox, a.oy, a.oz);
+    s = launch_forwardproject(a, plan, stream);
+    fdk_status s2 = device_free_async(d_index, stream);
+    fdk_status s3 = device_free_async(d_world, stream);
+    if (s != FDK_OK) return s;
+    return s2 != FDK_OK ? s2 : s3;
+}
+
+extern "C" fdk_status fdk_filter(const fdk_stack* sg, const float* raw, float* out, double du,
+                                 double dv, double sod, double sdd, double u_off, double v_off,
+                                 double arc, int32_t np_total, void* stream)
+{
+    fdk_status s = validate_stack(sg, false);
+    if (s != FDK_OK) return s;
+    if (!raw || !out) return fail(FDK_E_INVALID, "raw/out pointer is NULL");
+    if (raw == out) return fail(FDK_E_INVALID, "raw and out must not overlap");
+    if (!(du > 0) || !(dv > 0) || !(sod > 0) || !(sdd > 0) || !std::isfinite(du) ||
+        !std::isfinite(dv) || !std::isfinite(sod) || !std::isfinite(sdd) ||
+        !std::isfinite(u_off) || !std::isfinite(v_off) || !std::isfinite(arc))
+        return fail(FDK_E_INVALID, "pitches and distances must be positive and finite");
+    if (np_total <= 0) return fail(FDK_E_INVALID, "np_total must be positive");
+    if (sg->nw > 65536) return fail(FDK_E_UNSUPPORTED, "rows longer than 65536 pixels");
+    FilterLaunch a;
+    a.raw = raw;
+    a.out = out;
+    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+    a.du = du; a.dv = dv; a.sod = sod; a.sdd = sdd; a.u_off = u_off; a.v_off = v_off;
+    a.arc = arc;
+    a.np_total = np_total;
+    return launch_filter(a, stream);
+}
+
+extern "C" fdk_status fdk_quantize_f16(int32_t np, int32_t nh, int32_t nw, const float* in,
+                                       uint16_t* out, float* scale, void* stream)
+{
+    if (np <= 0 || nh <= 0 || nw <= 0) return fail(FDK_E_INVALID, "sizes must be positive");
+    if (!in || !out || !scale) return fail(FDK_E_INVALID, "in/out/scale pointer is NULL");
+    if ((double)np * nh * nw > 9.0e15 / 4) return fail(FDK_E_INVALID, "stack size overflows");
+    if (np > 65535) return fail(FDK_E_UNSUPPORTED, "more than 65535 views in one call");
+    return launch_quantize_f16(np, (int64_t)nh * nw, in, out, scale, stream);
+}
+
+extern "C" fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, const fdk_stack* sg,
+                                          float* proj, double arc, double theta0, double sod,
+                                          double sdd, double du, double dv, double u_off,
+                                          double v_off, int32_t view_begin, int32_t np_total,
+                                          void* stream)
+{
+    fdk_status s = validate_stack(sg, false);
+    if (s != FDK_OK) return s;
+    if (!proj) return fail(FDK_E_INVALID, "projection pointer is NULL");
+    if (n_ell < 0 || (n_ell > 0 && !ell)) return fail(FDK_E_INVALID, "ellipsoid table is NULL");
+    if (n_ell > 4096) return fail(FDK_E_UNSUPPORTED, "more than 4096 ellipsoids");
+    if (!(du > 0) || !(dv > 0) || !(sod > 0) || !(sdd > 0) || !std::isfinite(arc) ||
+        !std::isfinite(theta0) || !std::isfinite(u_off) || !std::isfinite(v_off))
+        return fail(FDK_E_INVALID, "pitches and distances must be positive and finite");
+    if (np_total <= 0 || view_begin < 0 || (int64_t)view_begin + sg->np > np_total)
+        return fail(FDK_E_INVALID, "views outside [0, np_total)");
+    for (int64_t q = 0; q < (int64_t)n_ell * 16; ++q)
+        if (!std::isfinite(ell[q])) return fail(FDK_E_INVALID, "ellipsoid entries must be finite");
+    for (int32_t e = 0; e < n_ell; ++e)
+        if (!(ell[16 * e + 3] > 0 && ell[16 * e + 4] > 0 && ell[16 * e + 5] > 0))
+            return fail(FDK_E_INVALID, "ellipsoid semi-axes must be positive");
+    if (sg->np > 65535) return fail(FDK_E_UNSUPPORTED, "more than 65535 views in one call");
+    if (n_ell == 0) return FDK_OK;
+    // unit-sphere frame of each ellipsoid: T = diag(1/axes) R^T (rows of T)
+    std::vector<double> tab((size_t)n_ell * 16, 0.0);
+    for (int32_t e = 0; e < n_ell; ++e) {
+        const double* E = ell + 16 * (size_t)e;
+        double* t = tab.data() + 16 * (size_t)e;
+        t[0] = E[0]; t[1] = E[1]; t[2] = E[2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) t[3 + 3 * i + j] = E[6 + 3 * j + i] / E[3 + i];
+        t[12] = E[15];
+    }
+    void* d_ell = nullptr;
+    s = upload_async(tab.data(), tab.size() * sizeof(double), stream, &d_ell);
+    if (s != FDK_OK) return s;
+    PhantomLaunch a;
+    a.ell = (const double*)d_ell;
+    a.n_ell = n_ell;
+    a.proj = proj;
+    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+    a.view_begin = view_begin;
+    a.np_total = np_total;
+    a.arc = arc; a.theta0 = theta0; a.sod = sod; a.sdd = sdd; a.du = du; a.dv = dv;
+    a.u_off = u_off; a.v_off = v_off;
+    s = launch_phantom(a, stream);
+    fdk_status s2 = device_free_async(d_ell, stream);
+    return s != FDK_OK ? s : s2;
+}

@@ -1,0 +1,302 @@
+// Host-side geometry: validation, FP64 matrix composition, the circular-orbit
+// matrix helper and the footprint-driven launch plan of the back-projector.
+// No HIP call is made in this file.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <sstream>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace fdk {
+
+void compose_index_matrices(const fdk_volume& vg, int32_t np, const double* mats,
+                            std::vector<IndexMatrix>& out)
+{
+    // Voxel (i,j,k) centre = (dx i + ox, dy j + oy, dz k + oz).
+    const double ox = vg.cx - 0.5 * (vg.nx - 1) * vg.dx;
+    const double oy = vg.cy - 0.5 * (vg.ny - 1) * vg.dy;
+    const double oz = vg.cz - 0.5 * (vg.nz - 1) * vg.dz;
+    out.resize(np);
+    for (int32_t s = 0; s < np; ++s) {
+        const double* P = mats + 12 * (size_t)s;
+        double* M = out[s].m;
+        for (int r = 0; r < 3; ++r) {
+            const double* p = P + 4 * r;
+            M[4 * r + 0] = p[0] * vg.dx;
+            M[4 * r + 1] = p[1] * vg.dy;
+            M[4 * r + 2] = p[2] * vg.dz;
+            M[4 * r + 3] = p[0] * ox + p[1] * oy + p[2] * oz + p[3];
+        }
+    }
+}
+
+fdk_status validate_volume(const fdk_volume* vg)
+{
+    if (!vg) return fail(FDK_E_INVALID, "volume geometry is NULL");
+    if (vg->nx <= 0 || vg->ny <= 0 || vg->nz <= 0)
+        return fail(FDK_E_INVALID, "volume dimensions must be positive");
+    if (!(vg->dx > 0 && vg->dy > 0 && vg->dz > 0) || !std::isfinite(vg->dx) ||
+        !std::isfinite(vg->dy) || !std::isfinite(vg->dz))
+        return fail(FDK_E_INVALID, "voxel pitch must be positive and finite");
+    if (!std::isfinite(vg->cx) || !std::isfinite(vg->cy) || !std::isfinite(vg->cz))
+        return fail(FDK_E_INVALID, "volume centre must be finite");
+    const double n = (double)vg->nx * vg->ny * vg->nz;
+    if (n > 9.0e15 / 4) return fail(FDK_E_INVALID, "volume size overflows");
+    return FDK_OK;
+}
+
+fdk_status validate_stack(const fdk_stack* sg, bool allow_f16)
+{
+    if (!sg) return fail(FDK_E_INVALID, "stack geometry is NULL");
+    if (sg->np <= 0 || sg->nh <= 0 || sg->nw <= 0)
+        return fail(FDK_E_INVALID, "stack dimensions must be positive");
+    if (sg->dtype != FDK_F32 && sg->dtype != FDK_F16)
+        return fail(FDK_E_INVALID, "unknown stack dtype");
+    if (sg->dtype == FDK_F16 && !allow_f16)
+        return fail(FDK_E_UNSUPPORTED, "binary16 stacks are accepted by the back-projector only");
+    if ((double)sg->np * sg->nh * sg->nw > 9.0e15 / 4)
+        return fail(FDK_E_INVALID, "stack size overflows");
+    if (sg->nh >= (1 << 24) || sg->nw >= (1 << 24))
+        return fail(FDK_E_UNSUPPORTED, "detector larger than 2^24 pixels per axis");
+    return FDK_OK;
+}
+
+fdk_status validate_geometry(const fdk_volume& vg, const fdk_stack& sg, const double* mats,
+                             std::vector<IndexMatrix>* composed)
+{
+    if (!mats) return fail(FDK_E_INVALID, "matrix array is NULL");
+    for (int64_t q = 0; q < (int64_t)sg.np * 12; ++q)
+        if (!std::isfinite(mats[q])) return fail(FDK_E_INVALID, "matrix entries must be finite");
+    std::vector<IndexMatrix> local;
+    std::vector<IndexMatrix>& M = composed ? *composed : local;
+    compose_index_matrices(vg, sg.np, mats, M);
+    const double ci[2] = {0.0, (double)(vg.nx - 1)};
+    const double cj[2] = {0.0, (double)(vg.ny - 1)};
+    for (int32_t s = 0; s < sg.np; ++s) {
+        const double* m = M[s].m;
+        // u w and w must not depend on k (detector V-axis parallel to the
+        // rotation axis): entries (0,2) and (2,2) vanish.
+        const double n0 = std::fabs(m[0]) + std::fabs(m[1]) + std::fabs(m[2]) + std::fabs(m[3]);
+        const double n2 = std::fabs(m[8]) + std::fabs(m[9]) + std::fabs(m[10]) + std::fabs(m[11]);
+        if (std::fabs(m[2]) > 1e-12 * n0 || std::fabs(m[10]) > 1e-12 * n2) {
+            std::ostringstream os;
+            os << "view " << s << ": u*w or w depends on the slice index (matrix entries (0,2)/(2,2)"
+               << " not zero); the detector V-axis must be parallel to the volume z axis";
+            return fail(FDK_E_GEOMETRY, os.str());
+        }
+        // w is affine in (i, j): positive at the four corner columns means
+        // positive over the whole volume (no voxel behind the source).
+        for (double i : ci)
+            for (double j : cj) {
+                const double w = m[8] * i + m[9] * j + m[11];
+                if (!(w > 0)) {
+                    std::ostringstream os;
+                    os << "view " << s << ": depth w <= 0 at volume corner column (" << i << ", "
+                       << j << ")";
+                    return fail(FDK_E_GEOMETRY, os.str());
+                }
+                const double u = (m[0] * i + m[1] * j + m[3]) / w;
+                const double v0 = (m[4] * i + m[5] * j + m[7]) / w;
+                const double v1 = (m[4] * i + m[5] * j + m[6] * (vg.nz - 1) + m[7]) / w;
+                if (!(std::fabs(u) < 4.0e6 && std::fabs(v0) < 4.0e6 && std::fabs(v1) < 4.0e6))
+                    return fail(FDK_E_UNSUPPORTED,
+                                "volume projects more than 4e6 pixels away from the detector");
+            }
+    }
+    return FDK_OK;
+}
+
+// ------------------------------------------------------------------ plan
+
+const int kPitches[] = {48, 80, 112, 144, 176, 208, 240};
+const int kNumPitches = (int)(sizeof(kPitches) / sizeof(kPitches[0]));
+
+namespace {
+
+struct Extent {
+    int cols = 0;   // max over blocks/views of floor(umax) - floor(umin) + 4
+    int rows = 0;   // upper bound of floor(vmax) - floor(vmin) + 4 over blocks/views
+};
+
+// Footprint of every (xy tile, view) for a given number of slices per block.
+// The kernel computes, per block and view, from the four corner columns of its
+// tile and the two end slices of its chunk:
+//   cols = floor(umax) - floor(umin) + 4,  rows = floor(vmax) - floor(vmin) + 4.
+// The width does not depend on the chunk.  The height of a chunk is a convex
+// function of the chunk start (max of affine minus min of affine), so its
+// maximum is at the first or the last chunk; floor(a) - floor(b) <=
+// floor(a - b) + 1 bounds the floors.
+Extent footprint(const fdk_volume& vg, const std::vector<IndexMatrix>& M, int kz)
+{
+    Extent e;
+    const int ntx = (vg.nx + kTile - 1) / kTile, nty = (vg.ny + kTile - 1) / kTile;
+    const int nch = (vg.nz + kz - 1) / kz;
+    const double kA[2] = {0.0, (double)((nch - 1) * kz)};
+    double umax_ext = 0, vmax_ext = 0;
+    int cols = 0;
+    for (size_t s = 0; s < M.size(); ++s) {
+        const double* m = M[s].m;
+        for (int ty = 0; ty < nty; ++ty) {
+            const int j0 = ty * kTile, nj = std::min(kTile, vg.ny - j0);
+            const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
+            for (int tx = 0; tx < ntx; ++tx) {
+                const int i0 = tx * kTile, ni = std::min(kTile, vg.nx - i0);
+                const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
+                double umin = 1e300, umax = -1e300;
+                double vlo[2] = {1e300, 1e300}, vhi[2] = {-1e300, -1e300};
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const double w = m[8] * ii[a] + m[9] * jj[b] + m[11];
+                        const double rw = 1.0 / w;
+                        const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) * rw;
+                        umin = std::min(umin, u);
+                        umax = std::max(umax, u);
+                        const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
+                        for (int c = 0; c < 2; ++c) {
+                            const double v0 = (A + m[6] * kA[c]) * rw;
+                            const double v1 = (A + m[6] * (kA[c] + kz - 1)) * rw;
+                            vlo[c] = std::min(vlo[c], std::min(v0, v1));
+                            vhi[c] = std::max(vhi[c], std::max(v0, v1));
+                        }
+                    }
+                cols = std::max(cols, (int)(std::floor(umax) - std::floor(umin)) + 4);
+                umax_ext = std::max(umax_ext, umax - umin);
+                for (int c = 0; c < 2; ++c) vmax_ext = std::max(vmax_ext, vhi[c] - vlo[c]);
+            }
+        }
+    }
+    (void)umax_ext;
+    e.cols = cols + 1;                                       // host/device rounding slack
+    e.rows = (int)std::floor(vmax_ext) + 1 + 4 + 1;
+    return e;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t q = 0; q < n; ++q) {
+        h ^= b[q];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::mutex g_plan_mu;
+std::list<std::pair<uint64_t, BpPlan>> g_plans;   // most recent first
+
+int env_int(const char* name, int dflt)
+{
+    const char* s = std::getenv(name);
+    if (!s || !*s) return dflt;
+    return std::atoi(s);
+}
+
+}  // namespace
+
+fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
+                        const std::vector<IndexMatrix>& M, BpPlan& plan)
+{
+    const int kz_force = env_int("FDK_BP_KZ", 0);
+    const int lds_budget = env_int("FDK_BP_LDS_BUDGET", 48 * 1024);
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &vg.nx, sizeof(int32_t) * 3);
+    h = fnv1a(h, &sg.np, sizeof(int32_t) * 3);
+    h = fnv1a(h, &kz_force, sizeof(int));
+    h = fnv1a(h, &lds_budget, sizeof(int));
+    h = fnv1a(h, M.data(), M.size() * sizeof(IndexMatrix));
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (auto it = g_plans.begin(); it != g_plans.end(); ++it)
+            if (it->first == h) {
+                plan = it->second;
+                g_plans.splice(g_plans.begin(), g_plans, it);
+                return FDK_OK;
+            }
+    }
+    const int cands[3] = {32, 16, 8};
+    const int table_bytes = kViewBatch * kViewRec * 4;
+    BpPlan best;
+    bool found = false;
+    for (int q = 0; q < 3 && !found; ++q) {
+        const int kz = cands[q];
+        if (kz_force && kz != kz_force) continue;
+        Extent e = footprint(vg, M, kz);
+        int pitch = 0;
+        for (int p = 0; p < kNumPitches; ++p)
+            if (kPitches[p] >= e.cols) { pitch = kPitches[p]; break; }
+        if (!pitch) continue;
+        const int64_t bytes = (int64_t)e.rows * pitch * 4 + table_bytes;
+        const bool last = (q == 2) || (kz_force == kz);
+        if (bytes <= lds_budget || (last && bytes <= 150 * 1024) || (kz_force == kz && bytes <= 150 * 1024)) {
+            best.kz = kz;
+            best.pitch = pitch;
+            best.rows = e.rows;
+            best.cols = e.cols;
+            best.lds_bytes = bytes;
+            found = true;
+        }
+    }
+    if (!found)
+        return fail(FDK_E_UNSUPPORTED,
+                    "projection footprint of a 16x16x8 voxel block does not fit in LDS "
+                    "(magnification too large for the detector pitch)");
+    best.ntx = (vg.nx + kTile - 1) / kTile;
+    best.nty = (vg.ny + kTile - 1) / kTile;
+    best.ntiles_pad = ((best.ntx * best.nty + 7) / 8) * 8;
+    best.nchunks = (vg.nz + best.kz - 1) / best.kz;
+    best.blocks = (int64_t)best.ntiles_pad * best.nchunks;
+    plan = best;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plans.emplace_front(h, best);
+    if (g_plans.size() > 32) g_plans.pop_back();
+    return FDK_OK;
+}
+
+}  // namespace fdk
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" fdk_status fdk_circular_matrices(int32_t np, double arc, double theta0, double sod,
+                                            double sdd, int32_t nh, int32_t nw, double du,
+                                            double dv, double u_off, double v_off,
+                                            double* mats_out)
+{
+    using namespace fdk;
+    if (!mats_out) return fail(FDK_E_INVALID, "mats_out is NULL");
+    if (np <= 0 || nh <= 0 || nw <= 0) return fail(FDK_E_INVALID, "sizes must be positive");
+    if (!(sod > 0) || !(sdd > 0) || !(du > 0) || !(dv > 0) || !std::isfinite(arc) ||
+        !std::isfinite(theta0) || !std::isfinite(u_off) || !std::isfinite(v_off) ||
+        !std::isfinite(sod) || !std::isfinite(sdd))
+        return fail(FDK_E_INVALID, "distances and pitches must be positive and finite");
+    // Pinhole camera of a flat detector: project onto the plane at distance
+    // sdd from the source along the central ray, in units of pixels, and
+    // divide the homogeneous coordinate by sod so that w = 1 on the axis.
+    const double mag = sdd / sod;
+    const double cu = 0.5 * (nw - 1) + u_off, cv = 0.5 * (nh - 1) + v_off;
+    for (int32_t s = 0; s < np; ++s) {
+        const double th = theta0 + arc * (double)s / (double)np;
+        const double c = std::cos(th), sn = std::sin(th);
+        double* m = mats_out + 12 * (size_t)s;
+        // depth row: w = (sod - x cos - y sin) / sod
+        m[8] = -c / sod;
+        m[9] = -sn / sod;
+        m[10] = 0.0;
+        m[11] = 1.0;
+        // u w = mag (-x sin + y cos) / du + cu w
+        m[0] = -mag * sn / du + cu * m[8];
+        m[1] = mag * c / du + cu * m[9];
+        m[2] = 0.0;
+        m[3] = cu;
+        // v w = mag z / dv + cv w
+        m[4] = cv * m[8];
+        m[5] = cv * m[9];
+        m[6] = mag / dv;
+        m[7] = cv;
+    }
+    return FDK_OK;
+}

@@ -1,0 +1,117 @@
+// Internal declarations shared by the host library and the kernel launchers.
+// Not part of the ABI (the ABI is include/fdk.h).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fdk.h"
+
+namespace fdk {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+fdk_status fail(fdk_status code, const std::string& msg);
+
+// ---------------------------------------------------------------- geometry
+// Index-space matrix of one view: maps (i, j, k, 1) to (u w, v w, w).
+struct IndexMatrix {
+    double m[12];
+};
+
+// Compose world-mm matrices with the voxel grid (FP64): M = P V, where V maps
+// voxel indices to the world position of the voxel centre.
+void compose_index_matrices(const fdk_volume& vg, int32_t np, const double* mats,
+                            std::vector<IndexMatrix>& out);
+
+// Host-side checks shared by every volume<->stack operator.  Returns FDK_OK or
+// the error (with the message set).  Makes no HIP call.
+fdk_status validate_volume(const fdk_volume* vg);
+fdk_status validate_stack(const fdk_stack* sg, bool allow_f16);
+fdk_status validate_geometry(const fdk_volume& vg, const fdk_stack& sg, const double* mats,
+                             std::vector<IndexMatrix>* composed);
+
+// ---------------------------------------------------------------- BP plan
+constexpr int kTile = 16;            // columns per block along x and along y
+constexpr int kThreads = kTile * kTile;
+constexpr int kViewBatch = 64;       // views whose per-block constants are built at once
+constexpr int kViewRec = 16;         // 32-bit words per view record in LDS
+
+struct BpPlan {
+    int kz = 0;          // slices per thread (register accumulators)
+    int pitch = 0;       // LDS row pitch in floats (compile-time in the kernel)
+    int rows = 0;        // LDS rows (maximum footprint height over all blocks/views)
+    int cols = 0;        // maximum footprint width
+    int ntx = 0, nty = 0, ntiles_pad = 0, nchunks = 0;
+    int64_t lds_bytes = 0;
+    int64_t blocks = 0;
+};
+
+// Footprint-driven launch plan (cached by a hash of the inputs).
+fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
+                        const std::vector<IndexMatrix>& M, BpPlan& plan);
+
+// Pitches the kernel is instantiated for (floats per LDS row).
+extern const int kPitches[];
+extern const int kNumPitches;
+
+// ---------------------------------------------------------------- runtime
+// Copy `bytes` of host memory to a new stream-ordered device allocation.
+// The host buffer may be reused as soon as the call returns.
+fdk_status upload_async(const void* host, size_t bytes, void* stream, void** dev);
+fdk_status device_alloc_async(size_t bytes, void* stream, void** dev);
+fdk_status device_free_async(void* dev, void* stream);
+fdk_status check_launch(const char* what);
+
+// ---------------------------------------------------------------- launchers
+// FP64 composition on the device: M_s = P_s V with V the voxel-index -> world
+// map (pitch d*, world position o* of voxel (0,0,0)).  P, M: [np][12].
+fdk_status launch_compose(const double* P, double* M, int32_t np, double dx, double dy,
+                          double dz, double ox, double oy, double oz, void* stream);
+
+struct BpLaunch {
+    const void* proj;        // [np][nh][nw] f32 or f16
+    const float* scale;      // [np] or nullptr
+    const double* mats_world;// device [np][12] world matrices (uploaded)
+    double* mats_index;      // device [np][12] scratch for the composed matrices
+    float* vol;              // slab base
+    int32_t nx, ny, nz, np, nh, nw;
+    int32_t k_begin, k_end;  // slab [k_begin, k_end) of the full volume
+    double dx, dy, dz, ox, oy, oz;  // voxel pitch and world position of voxel (0,0,0)
+    int f16;
+};
+fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* stream);
+
+struct FpLaunch {
+    const float* vol;
+    float* proj;
+    const double* mats_world;
+    double* mats_index;
+    int32_t nx, ny, nz, np, nh, nw;
+    double dx, dy, dz, ox, oy, oz;
+};
+fdk_status launch_forwardproject(const FpLaunch& a, const BpPlan& plan, void* stream);
+
+struct FilterLaunch {
+    const float* raw;
+    float* out;
+    int32_t np, nh, nw;
+    double du, dv, sod, sdd, u_off, v_off, arc;
+    int32_t np_total;
+};
+fdk_status launch_filter(const FilterLaunch& a, void* stream);
+
+fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16_t* out,
+                               float* scale, void* stream);
+
+struct PhantomLaunch {
+    const double* ell;       // device [n_ell][16]
+    int32_t n_ell;
+    float* proj;
+    int32_t np, nh, nw, view_begin, np_total;
+    double arc, theta0, sod, sdd, du, dv, u_off, v_off;
+};
+fdk_status launch_phantom(const PhantomLaunch& a, void* stream);
+
+}  // namespace fdk

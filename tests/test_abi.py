@@ -1,0 +1,231 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects bad arguments on the host before any HIP call.
+
+Device pointers here are fake non-NULL addresses: every case is rejected by
+host-side validation before the library would touch them."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import geometry as og
+import workloads as wl
+
+fdk = pytest.importorskip("paper_2104_13248_amd")
+from paper_2104_13248_amd import _lib  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = ctypes.c_void_p(0x10000)
+OK, E_INVALID, E_GEOMETRY, E_UNSUPPORTED = 0, -1, -2, -3
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fdk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_match_header():
+    names = header_functions()
+    assert "fdk_backproject" in names and "fdk_forwardproject" in names and "fdk_filter" in names
+    for n in names:
+        assert hasattr(_lib.lib, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_symbols_via_nm():
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (fdk_\w+)", out))
+    assert set(header_functions()) <= exported
+
+
+def _geom(cfg):
+    vg = _lib.volume_struct(cfg["shape"], cfg["voxel"])
+    sg = _lib.stack_struct(cfg["np"], cfg["nh"], cfg["nw"])
+    m = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    return vg, sg, np.ascontiguousarray(m)
+
+
+def call_bp(vg, sg, m, vol=FAKE, proj=FAKE, scale=None):
+    return _lib.lib.fdk_backproject(ctypes.byref(vg) if vg is not None else None, vol,
+                                    ctypes.byref(sg) if sg is not None else None, proj, scale,
+                                    _lib.ptr(m) if m is not None else None, None)
+
+
+C1 = wl.CONFIGS["c1"]
+
+
+def test_null_pointers_rejected():
+    vg, sg, m = _geom(C1)
+    assert call_bp(None, sg, m) == E_INVALID
+    assert call_bp(vg, None, m) == E_INVALID
+    assert call_bp(vg, sg, None) == E_INVALID
+    assert call_bp(vg, sg, m, vol=None) == E_INVALID
+    assert call_bp(vg, sg, m, proj=None) == E_INVALID
+    assert "NULL" in _lib.lib.fdk_last_error().decode()
+
+
+def test_bad_sizes_rejected():
+    vg, sg, m = _geom(C1)
+    for field in ("nx", "ny", "nz"):
+        bad = _lib.volume_struct(C1["shape"], C1["voxel"])
+        setattr(bad, field, 0)
+        assert call_bp(bad, sg, m) == E_INVALID
+    bad = _lib.volume_struct(C1["shape"], (1.0, -1.0, 1.0))
+    assert call_bp(bad, sg, m) == E_INVALID
+    bad = _lib.volume_struct(C1["shape"], (1.0, float("nan"), 1.0))
+    assert call_bp(bad, sg, m) == E_INVALID
+    for field in ("np", "nh", "nw"):
+        s2 = _lib.stack_struct(C1["np"], C1["nh"], C1["nw"])
+        setattr(s2, field, -3)
+        assert call_bp(vg, s2, m) == E_INVALID
+
+
+def test_dtype_and_scale_rules():
+    vg, sg, m = _geom(C1)
+    s_bad = _lib.stack_struct(C1["np"], C1["nh"], C1["nw"], 7)
+    assert call_bp(vg, s_bad, m) == E_INVALID
+    s16 = _lib.stack_struct(C1["np"], C1["nh"], C1["nw"], _lib.FDK_F16)
+    assert call_bp(vg, s16, m, scale=None) == E_INVALID            # f16 needs scales
+    assert call_bp(vg, sg, m, scale=FAKE) == E_INVALID             # f32 takes none
+    # the forward projector takes float32 only
+    assert _lib.lib.fdk_forwardproject(ctypes.byref(vg), FAKE, ctypes.byref(s16), FAKE,
+                                       _lib.ptr(m), None) == E_UNSUPPORTED
+
+
+def test_non_finite_matrix_rejected():
+    vg, sg, m = _geom(C1)
+    m = m.copy()
+    m[3, 1, 2] = np.inf
+    assert call_bp(vg, sg, m) == E_INVALID
+
+
+def test_tilted_detector_rejected():
+    """u w or w depending on k breaks the hoisting the kernels rely on."""
+    vg, sg, m = _geom(C1)
+    m1 = m.copy()
+    m1[5, 0, 2] = 1e-3                       # u w depends on z
+    assert call_bp(vg, sg, m1) == E_GEOMETRY
+    m2 = m.copy()
+    m2[0, 2, 2] = 1e-4                       # w depends on z
+    assert call_bp(vg, sg, m2) == E_GEOMETRY
+    assert "slice index" in _lib.lib.fdk_last_error().decode()
+    m3 = m.copy()
+    m3[0, 0, 2] = 1e-16                      # round-off sized entries are accepted
+    vg2 = _lib.volume_struct(C1["shape"], C1["voxel"])
+    out = (ctypes.c_int64 * 8)()
+    assert _lib.lib.fdk_bp_plan(ctypes.byref(vg2), ctypes.byref(sg), _lib.ptr(m3),
+                                ctypes.cast(out, ctypes.c_void_p)) == OK
+
+
+def test_voxel_behind_source_rejected():
+    cfg = dict(C1, scan=dict(C1["scan"], sod=20.0, sdd=40.0))  # source inside the FOV
+    vg, sg, m = _geom(cfg)
+    assert call_bp(vg, sg, m) == E_GEOMETRY
+    assert "w <= 0" in _lib.lib.fdk_last_error().decode()
+
+
+def test_slab_range_rejected():
+    vg, sg, m = _geom(C1)
+    f = _lib.lib.fdk_backproject_slab
+    for kb, kc in [(-1, 4), (0, 0), (60, 5), (64, 1)]:
+        assert f(ctypes.byref(vg), kb, kc, FAKE, ctypes.byref(sg), FAKE, None, _lib.ptr(m),
+                 None) == E_INVALID
+
+
+def test_filter_quantize_phantom_validation():
+    sg = _lib.stack_struct(4, 8, 16)
+    L = _lib.lib
+    assert L.fdk_filter(ctypes.byref(sg), None, FAKE, 1.0, 1.0, 500.0, 1000.0, 0, 0, 6.28, 4,
+                        None) == E_INVALID
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, FAKE, 1.0, 1.0, 500.0, 1000.0, 0, 0, 6.28, 4,
+                        None) == E_INVALID                      # raw == out
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, ctypes.c_void_p(0x20000), -1.0, 1.0, 500.0,
+                        1000.0, 0, 0, 6.28, 4, None) == E_INVALID
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, ctypes.c_void_p(0x20000), 1.0, 1.0, 500.0,
+                        1000.0, 0, 0, 6.28, 0, None) == E_INVALID
+    assert L.fdk_quantize_f16(0, 8, 16, FAKE, FAKE, FAKE, None) == E_INVALID
+    assert L.fdk_quantize_f16(4, 8, 16, FAKE, FAKE, None, None) == E_INVALID
+    ell = np.zeros((2, 16))
+    ell[:, 3:6] = 1.0
+    scan = C1["scan"]
+    args = [scan["arc"], scan["theta0"], scan["sod"], scan["sdd"], scan["du"], scan["dv"],
+            scan["u_off"], scan["v_off"]]
+    assert L.fdk_phantom_project(_lib.ptr(ell), 2, ctypes.byref(sg), FAKE, *args, 2, 5,
+                                 None) == E_INVALID             # views past np_total
+    bad = ell.copy()
+    bad[1, 4] = 0.0
+    assert L.fdk_phantom_project(_lib.ptr(bad), 2, ctypes.byref(sg), FAKE, *args, 0, 4,
+                                 None) == E_INVALID             # zero semi-axis
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5):
+        assert _lib.lib.fdk_status_string(code).decode()
+    assert _lib.lib.fdk_status_string(42).decode() == "unknown status"
+
+
+def test_circular_matrices_match_ray_plane_geometry():
+    """The library's matrix helper against the oracle's ray/plane intersection
+    (an independent derivation of the same scanner)."""
+    scan = dict(sod=510.0, sdd=990.0, du=0.7, dv=1.1, arc=2 * math.pi, theta0=0.4,
+                u_off=1.5, v_off=-2.25)
+    npv, nh, nw = 11, 50, 70
+    m = fdk.circular_matrices(npv, scan["arc"], scan["theta0"], scan["sod"], scan["sdd"], nh, nw,
+                              scan["du"], scan["dv"], scan["u_off"], scan["v_off"])
+    th = og.view_angles(npv, scan["arc"], scan["theta0"])
+    pts = np.random.default_rng(3).uniform(-60, 60, (40, 3))
+    for s in range(npv):
+        uvw = oracle.project_points(th[s], scan, nh, nw, pts)
+        q = np.concatenate([pts, np.ones((40, 1))], 1) @ m[s].T
+        np.testing.assert_allclose(q[:, 0] / q[:, 2], uvw[:, 0], atol=1e-9)
+        np.testing.assert_allclose(q[:, 1] / q[:, 2], uvw[:, 1], atol=1e-9)
+        np.testing.assert_allclose(q[:, 2], uvw[:, 2], atol=1e-12)
+    assert np.all(m[:, 0, 2] == 0) and np.all(m[:, 2, 2] == 0)
+    with pytest.raises(fdk.FdkError):
+        fdk.circular_matrices(4, scan["arc"], 0.0, -1.0, 990.0, nh, nw, 1.0, 1.0)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
+def test_plan_covers_every_footprint(name):
+    """The launch plan's LDS window bounds the footprint of every block and
+    view (checked here by brute force over all tiles, chunks and views, in
+    FP64, with the kernel's own footprint rule)."""
+    cfg = wl.CONFIGS[name]
+    m = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], cfg["np"], cfg["nh"], cfg["nw"], m)
+    M = og.index_matrices(m, cfg["shape"], cfg["voxel"])
+    nz, ny, nx = cfg["shape"]
+    kz = plan["kz"]
+    step = max(1, cfg["np"] // 64)
+    M = M[::step]
+    i0 = np.arange(0, nx, 16)
+    j0 = np.arange(0, ny, 16)
+    k0 = np.arange(0, nz, kz)
+    I = np.stack([i0, np.minimum(i0 + 15, nx - 1)], 1)          # [ntx, 2]
+    J = np.stack([j0, np.minimum(j0 + 15, ny - 1)], 1)
+    cols = rows = 0
+    for Ms in M:
+        ii = I[:, None, :, None]
+        jj = J[None, :, None, :]
+        w = Ms[2, 0] * ii + Ms[2, 1] * jj + Ms[2, 3]
+        u = (Ms[0, 0] * ii + Ms[0, 1] * jj + Ms[0, 3]) / w
+        umin = u.min(axis=(2, 3))
+        umax = u.max(axis=(2, 3))
+        cols = max(cols, int((np.floor(umax) - np.floor(umin)).max()) + 4)
+        A = Ms[1, 0] * ii + Ms[1, 1] * jj + Ms[1, 3]
+        for kc in k0:
+            v0 = (A + Ms[1, 2] * kc) / w
+            v1 = (A + Ms[1, 2] * (kc + kz - 1)) / w
+            vmin = np.minimum(v0, v1).min(axis=(2, 3))
+            vmax = np.maximum(v0, v1).max(axis=(2, 3))
+            rows = max(rows, int((np.floor(vmax) - np.floor(vmin)).max()) + 4)
+    assert cols <= plan["lds_pitch"]
+    assert rows <= plan["lds_rows"]
+    assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4

@@ -1,0 +1,182 @@
+"""Parity of the HIP back-projector with the FP64 oracle (MI355X).
+
+Every case feeds the same seeded host arrays to both sides.  FP32 tolerance:
+rel-L2 <= 1e-5; FP16-stored projections: rel-L2 <= 1e-3 against the oracle on
+the float32 stack (and <= 1e-5 against the oracle on the dequantised stack,
+which isolates the kernel's own error from the storage rounding).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import geometry as og
+import workloads as wl
+from helpers import c1_filtered, log, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdk = pytest.importorskip("paper_2104_13248_amd")
+
+TOL32 = 1e-5
+TOL16 = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def gpu_bp(proj, mats, shape, voxel, centre=(0.0, 0.0, 0.0), vol0=None, scale=None):
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda") if vol0 is None else \
+        torch.from_numpy(np.ascontiguousarray(vol0, dtype=np.float32)).cuda()
+    p = torch.from_numpy(np.ascontiguousarray(proj)).cuda()
+    s = None if scale is None else torch.from_numpy(np.ascontiguousarray(scale)).cuda()
+    fdk.backproject(vol, p, mats, voxel, centre, scale=s)
+    torch.cuda.synchronize()
+    return vol.cpu().numpy()
+
+
+def test_c1_phantom_f32():
+    cfg = wl.CONFIGS["c1"]
+    proj, mats = c1_filtered(0)
+    log("c1 phantom f32", cfg["shape"], proj.shape)
+    got = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"])
+    ref = oracle.backproject(proj, mats, cfg["shape"], cfg["voxel"])
+    e = rel(got, ref)
+    log("rel-L2", e)
+    assert e <= TOL32
+
+
+def test_c1_gaussian_f32():
+    """White-noise projections: the largest interpolation gradients."""
+    cfg = wl.CONFIGS["c1"]
+    proj = wl.gaussian(101, (cfg["np"], cfg["nh"], cfg["nw"]))
+    mats = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    got = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"])
+    ref = oracle.backproject(proj, mats, cfg["shape"], cfg["voxel"])
+    e = rel(got, ref)
+    log("c1 gaussian rel-L2", e)
+    assert e <= TOL32
+
+
+RAGGED = [
+    # shape (nz, ny, nx), (np, nh, nw), voxel, centre, scan overrides
+    ((7, 19, 33), (70, 45, 61), (0.9, 1.1, 1.3), (2.0, -3.0, 1.5),
+     dict(theta0=0.3, u_off=1.7, v_off=-2.2)),
+    ((1, 16, 16), (1, 40, 40), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), {}),
+    ((33, 17, 15), (129, 96, 80), (1.0, 1.0, 0.5), (0.0, 0.0, -4.0), dict(arc=math.pi)),
+    ((5, 1, 1), (3, 16, 16), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), {}),
+    ((40, 48, 48), (64, 30, 200), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0), dict(dv=2.0)),  # volume far off the detector rows
+]
+
+
+@pytest.mark.parametrize("case", range(len(RAGGED)))
+def test_ragged_shapes(case):
+    shape, (npv, nh, nw), voxel, centre, over = RAGGED[case]
+    scan = dict(wl.CONFIGS["c1"]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    proj = wl.gaussian(200 + case, (npv, nh, nw))
+    log("ragged", case, shape, (npv, nh, nw))
+    got = gpu_bp(proj, mats, shape, voxel, centre)
+    ref = oracle.backproject(proj, mats, shape, voxel, centre)
+    e = rel(got, ref)
+    log("rel-L2", e)
+    assert e <= TOL32
+
+
+def test_accumulates_into_volume():
+    cfg = wl.CONFIGS["c1"]
+    proj, mats = c1_filtered(0)
+    base = wl.gaussian(300, cfg["shape"])
+    got = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"], vol0=base)
+    ref = oracle.backproject(proj, mats, cfg["shape"], cfg["voxel"], vol=base.astype(np.float64))
+    assert rel(got, ref) <= TOL32
+
+
+def test_deterministic_bitwise():
+    cfg = wl.CONFIGS["c1"]
+    proj, mats = c1_filtered(0)
+    a = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"])
+    b = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"])
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_slabs_bitwise_equal_full():
+    """z-slab decomposition (the multi-device split) reproduces the full call."""
+    cfg = wl.shrink(wl.CONFIGS["c1"], shape=(70, 40, 36))
+    proj, mats = c1_filtered(0)
+    full = gpu_bp(proj, mats, cfg["shape"], cfg["voxel"])
+    p = torch.from_numpy(proj).cuda()
+    for k0, kc in [(0, 70), (0, 1), (5, 20), (31, 33), (69, 1), (32, 32), (17, 53)]:
+        slab = torch.zeros((kc,) + cfg["shape"][1:], dtype=torch.float32, device="cuda")
+        fdk.backproject_slab(slab, cfg["shape"], k0, p, mats, cfg["voxel"])
+        torch.cuda.synchronize()
+        got = slab.cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), full[k0:k0 + kc].view(np.uint32)), (k0, kc)
+
+
+def test_quantizer_bit_exact():
+    proj, _ = c1_filtered(0)
+    proj = proj.copy()
+    proj[3] = 0.0                                   # an all-zero view
+    proj[5] *= np.float32(1e-20)                    # tiny values (binary16 subnormals)
+    h_ref, s_ref = oracle.quantize_f16(proj)
+    h, s = fdk.quantize_f16(torch.from_numpy(proj).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), s_ref.view(np.uint32))
+    assert np.array_equal(h.cpu().numpy().view(np.uint16), h_ref.view(np.uint16))
+
+
+def test_c1_f16_storage():
+    cfg = wl.CONFIGS["c1"]
+    proj, mats = c1_filtered(0)
+    h, s = fdk.quantize_f16(torch.from_numpy(proj).cuda())
+    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, cfg["voxel"], scale=s)
+    torch.cuda.synchronize()
+    got = vol.cpu().numpy()
+    ref32 = oracle.backproject(proj, mats, cfg["shape"], cfg["voxel"])
+    h_np, s_np = h.cpu().numpy(), s.cpu().numpy()
+    ref16 = oracle.backproject(h_np, mats, cfg["shape"], cfg["voxel"], scale=s_np)
+    e32, e16 = rel(got, ref32), rel(got, ref16)
+    log("f16: vs oracle(f32) %.3e, vs oracle(dequantised) %.3e, storage-only %.3e"
+        % (e32, e16, rel(ref16, ref32)))
+    assert e32 <= TOL16
+    assert e16 <= TOL32
+
+
+def _sample_voxels(shape, n, seed):
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    pts = np.stack([rng.integers(0, nx, n), rng.integers(0, ny, n), rng.integers(0, nz, n)], 1)
+    corners = np.array([[i, j, k] for i in (0, nx - 1) for j in (0, ny - 1) for k in (0, nz - 1)])
+    edges = np.array([[nx // 2, 0, nz // 2], [0, ny // 2, 0], [nx - 1, ny - 1, nz // 2],
+                      [nx // 2, ny // 2, nz - 1]])
+    return np.concatenate([pts, corners, edges]).astype(np.int64)
+
+
+def test_c2_full_size_sampled():
+    """512^3 x 1024 views x 1024^2 (the benchmark launch), Gaussian
+    projections; sampled voxels against the oracle evaluated one by one."""
+    cfg = wl.CONFIGS["c2"]
+    log("c2: generating", (cfg["np"], cfg["nh"], cfg["nw"]))
+    proj = wl.gaussian(2001, (cfg["np"], cfg["nh"], cfg["nw"]))
+    mats = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    log("c2: gpu")
+    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    p = torch.from_numpy(proj).cuda()
+    fdk.backproject(vol, p, mats, cfg["voxel"])
+    torch.cuda.synchronize()
+    ijk = _sample_voxels(cfg["shape"], 384, 7)
+    got = vol[ijk[:, 2], ijk[:, 1], ijk[:, 0]].cpu().numpy()
+    del vol, p
+    log("c2: oracle on", len(ijk), "voxels")
+    ref = oracle.backproject_points(proj, mats, cfg["shape"], cfg["voxel"], ijk)
+    e = rel(got, ref)
+    log("c2 sampled rel-L2", e)
+    assert e <= TOL32

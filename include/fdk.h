@@ -186,9 +186,12 @@ fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, const fdk_stack
 
 /*
  * fdk_bp_plan -- host query of the launch the back-projector would use for
- * these inputs: out[0..7] = tile_x, tile_y, kz (slices per thread),
- * lds_pitch, lds_rows, lds_bytes per block, blocks, threads per block.
- * Validates exactly like fdk_backproject.  No HIP call.
+ * these inputs: out[0..9] = tile_x, tile_y, kz (slices per thread),
+ * lds_pitch (words per LDS row), lds_rows, lds_bytes per block, blocks,
+ * threads per block, rows_full (rows of the tallest whole-chunk footprint;
+ * taller than lds_rows means such footprints are staged per half-chunk),
+ * forward-projector lds_bytes per block.  Validates exactly like
+ * fdk_backproject.  No HIP call.
  */
 fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, const double* mats,
                        int64_t* out);

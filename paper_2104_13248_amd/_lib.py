@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfdk.so")
+# FDK_LIBRARY may name another build of the same library (e.g. a tuning build)
+LIB_PATH = os.environ.get("FDK_LIBRARY") or os.path.join(_PKG, "libfdk.so")
 
 FDK_F32 = 0
 FDK_F16 = 1

@@ -49,6 +49,8 @@ extern "C" fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, con
     out[5] = plan.lds_bytes;
     out[6] = plan.blocks;
     out[7] = kThreads;
+    out[8] = plan.rows_full;
+    out[9] = plan.fp_lds_bytes;
     return FDK_OK;
 }
 
@@ -67,6 +69,8 @@ extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin
         return fail(FDK_E_INVALID, "a scale array is only accepted with binary16 projections");
     if (k_begin < 0 || k_count <= 0 || (int64_t)k_begin + k_count > vg->nz)
         return fail(FDK_E_INVALID, "slab [k_begin, k_begin + k_count) outside the volume");
+    if ((int64_t)sg->nh * sg->nw * (sg->dtype == FDK_F16 ? 2 : 4) >= (1ll << 31))
+        return fail(FDK_E_UNSUPPORTED, "one view larger than 2 GiB");
     BpPlan plan;
     s = make_bp_plan(*vg, *sg, M, plan);
     if (s != FDK_OK) return s;

@@ -16,8 +16,12 @@
 //     LDS with zero padding (the local-memory staging of Section 3.2, without
 //     a per-update bounds check).  Each wave stages whole detector rows:
 //     float32 rows go straight from memory into LDS (buffer loads with the
-//     LDS-direct bit, no VGPR round trip); a buffer descriptor per row makes
-//     columns and rows outside the detector read as zero;
+//     LDS-direct bit, no VGPR round trip); out-of-range buffer offsets make
+//     columns outside the detector read as zero, rows outside it are zeroed;
+//   * the LDS tile is sized for nearly every (block, view) footprint; the
+//     rare taller ones (blocks near the source at a large cone angle) are
+//     staged and consumed in two half-chunks of slices, which keeps the LDS
+//     per block small and the occupancy high;
 //   * binary16 stacks are staged as (p[c], p[c+1]) pairs in one LDS word (the
 //     right neighbour arrives by a DPP lane shift), so one LDS read yields
 //     both horizontal taps and the lerps run as mixed-precision FMAs on the
@@ -78,55 +82,120 @@ struct BpArgs {
 };
 
 // Stage rows [r0, r0+R) x columns [c0, c0+C) of one view into the LDS tile
-// (row pitch PITCH words), zero outside the detector.  Wave w stages rows
-// w, w+4, ...; lanes run along the row.
+// (row pitch PITCH words), zero outside the detector.  Wave w stages rows w, w+4, ...; lanes run along the row.  One
+// buffer descriptor covers the view; a column outside the detector gets an
+// out-of-range offset (reads as zero), a row outside it is written as zeros.
 template <int PITCH, bool F16>
-__device__ __forceinline__ void stage_view(float* tile, const char* vbase, int nh, int nw,
-                                           int r0, int c0, int R, int C, int wave, int lane)
+__device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rsrc_t& rs, int nh,
+                                           unsigned row_bytes, int nw, int r0, int c0, int R, int C,
+                                           int wave, int lane)
 {
-    const unsigned row_bytes = (unsigned)nw * (F16 ? 2u : 4u);
+    constexpr int kWaves = kThreads / 64;
+    constexpr unsigned kOut = 0x80000000u;   // beyond any view: the load returns zero
+    unsigned* wtile = reinterpret_cast<unsigned*>(tile);
     if (!F16) {
-        for (int rr = wave; rr < R; rr += kThreads / 64) {
-            const int r = r0 + rr;
-            const bool ok = (unsigned)r < (unsigned)nh;
-            const char* rb = vbase + (ok ? (size_t)r * row_bytes : 0);
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void*)rb, 0, ok ? (int)row_bytes : 0, kBufferFlags);
-            for (int g = 0; g * 64 < C; ++g) {
-                if (g * 64 + lane < C) {
-                    // columns left of the detector wrap to huge unsigned
-                    // offsets and read as zero like those on the right
-                    const unsigned voff = (unsigned)(c0 + g * 64 + lane) * 4u;
-                    lds_void* dst = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + g * 64);
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff, 0, 0, 0);
+        for (int g = 0; g * 64 < C; ++g) {
+            const int cc = g * 64 + lane;
+            const int c = c0 + cc;
+            const unsigned voff = (unsigned)c < (unsigned)nw ? (unsigned)c * 4u : kOut;
+            const bool keep = cc < C;
+            for (int rr = wave; rr < R; rr += kWaves) {
+                const int r = r0 + rr;
+                if ((unsigned)r < (unsigned)nh) {
+                    if (keep) {
+                        lds_void* dst = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + g * 64);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dst, 4, voff,
+                                                                 (unsigned)r * row_bytes, 0, 0);
+                    }
+                } else if (keep) {
+                    wtile[rr * PITCH + cc] = 0u;
                 }
             }
         }
     } else {
-        // groups of 63 pairs: lane 63 only supplies the right neighbour of lane 62
-        for (int rr = wave; rr < R; rr += kThreads / 64) {
-            const int r = r0 + rr;
-            const bool ok = (unsigned)r < (unsigned)nh;
-            const char* rb = vbase + (ok ? (size_t)r * row_bytes : 0);
-            const __amdgpu_buffer_rsrc_t rs =
-                __builtin_amdgcn_make_buffer_rsrc((void*)rb, 0, ok ? (int)row_bytes : 0, kBufferFlags);
-            for (int g = 0; g * 63 < C; ++g) {
-                const int cc = g * 63 + lane;
-                const unsigned voff = (unsigned)(c0 + cc) * 2u;
-                const unsigned lo = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, 0, 0);
-                // DPP wave shift left by one lane: lane i receives (lane i+1) << 16
-                const unsigned pair =
-                    __builtin_amdgcn_update_dpp(0u, lo << 16, 0x130, 0xf, 0xf, false) | lo;
-                if (lane < 63 && cc < C)
-                    reinterpret_cast<unsigned*>(tile)[rr * PITCH + cc] = pair;
+        // Groups of 63 pairs: lane 63 only supplies the right neighbour of
+        // lane 62.  Rows are loaded kRowBatch at a time so that the loads of
+        // a batch are in flight together before the first one is consumed.
+        constexpr int kRowBatch = 8;
+        for (int g = 0; g * 63 < C; ++g) {
+            const int cc = g * 63 + lane;
+            const int c = c0 + cc;
+            const unsigned voff = (unsigned)c < (unsigned)nw ? (unsigned)c * 2u : kOut;
+            const bool keep = lane < 63 && cc < C;
+            for (int rb0 = wave; rb0 < R; rb0 += kWaves * kRowBatch) {
+                unsigned lo[kRowBatch];
+#pragma unroll
+                for (int b = 0; b < kRowBatch; ++b) {
+                    const int rr = rb0 + kWaves * b;
+                    const int r = r0 + rr;
+                    lo[b] = 0u;
+                    if (rr < R && (unsigned)r < (unsigned)nh)
+                        lo[b] = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, (unsigned)r * row_bytes, 0);
+                }
+#pragma unroll
+                for (int b = 0; b < kRowBatch; ++b) {
+                    const int rr = rb0 + kWaves * b;
+                    // DPP wave shift left by one lane: lane i receives (lane i+1) << 16
+                    const unsigned pair =
+                        __builtin_amdgcn_update_dpp(0u, lo[b] << 16, 0x130, 0xf, 0xf, false) | lo[b];
+                    if (keep && rr < R) wtile[rr * PITCH + cc] = pair;
+                }
             }
         }
     }
 }
 
+// KZ/2 consecutive updates kk = k0 + t, t = 0 .. KZ/2 - 1, of one column for
+// one view; v = v0 + t dv is the row coordinate relative to the half's origin,
+// whose LDS row address (plus the column) is `base`.  Tap loads run
+// kPrefetch updates ahead of their use.
 template <int KZ, int PITCH, bool F16>
-__global__ __launch_bounds__(kThreads) void bp_kernel(const BpArgs A)
+__device__ __forceinline__ void update_half(float (&acc)[KZ], int k0, unsigned base, float v0,
+                                            float dv, float fu, float W)
 {
+    constexpr int kPrefetch = KZ / 2 < 8 ? KZ / 2 : 8;
+#pragma unroll
+    for (int g0 = 0; g0 < KZ / 2; g0 += kPrefetch) {
+        float fv[kPrefetch];
+        unsigned t[kPrefetch][4];
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            const float v = fmaf((float)(g0 + q), dv, v0);
+            fv[q] = __builtin_amdgcn_fractf(v);
+            // row floor(v) (v >= 1 inside the tile): one 24-bit multiply-add
+            const lds_u32* p = (const lds_u32*)(size_t)(__umul24((unsigned)(int)v, 4u * PITCH) + base);
+            t[q][0] = p[0];
+            t[q][2] = p[PITCH];
+            if (!F16) {
+                t[q][1] = p[1];
+                t[q][3] = p[PITCH + 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            float h0, h1;
+            if (F16) {
+                h0 = lerp_pair_f16(t[q][0], fu);
+                h1 = lerp_pair_f16(t[q][2], fu);
+            } else {
+                const float p00 = __builtin_bit_cast(float, t[q][0]);
+                const float p01 = __builtin_bit_cast(float, t[q][1]);
+                const float p10 = __builtin_bit_cast(float, t[q][2]);
+                const float p11 = __builtin_bit_cast(float, t[q][3]);
+                h0 = fmaf(fu, p01 - p00, p00);
+                h1 = fmaf(fu, p11 - p10, p10);
+            }
+            acc[k0 + g0 + q] = fmaf(W, fmaf(fv[q], h1 - h0, h0), acc[k0 + g0 + q]);
+        }
+    }
+}
+
+// Four waves per SIMD: the register budget that, with the LDS tile of the
+// launch plan, keeps four or more blocks resident per CU.
+template <int KZ, int PITCH, bool F16>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bp_kernel(const BpArgs A)
+{
+    static_assert(KZ % 2 == 0, "slices are processed in two halves");
     extern __shared__ float smem[];
     float* tile = smem;                                       // [rows][PITCH] words
     ViewRec* vtab = reinterpret_cast<ViewRec*>(smem + A.rows * PITCH);
@@ -148,7 +217,8 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(const BpArgs A)
     const float di = (float)min(lx, ni - 1), dj = (float)min(ly, nj - 1);
 
     const char* proj = reinterpret_cast<const char*>(A.proj);
-    const size_t view_bytes = (size_t)A.nh * A.nw * (F16 ? 2 : 4);
+    const unsigned row_bytes = (unsigned)A.nw * (F16 ? 2u : 4u);
+    const unsigned view_bytes = row_bytes * (unsigned)A.nh;   // < 2^31, checked by the host
     const unsigned tile_base = lds_addr(tile);
 
     float acc[KZ];
@@ -161,16 +231,18 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(const BpArgs A)
         if (tid < nb) {
             const int s = sb + tid;
             const float sc = A.scale ? A.scale[s] : 1.0f;
-            view_record(A.M + 12 * (size_t)s, i0, j0, ni, nj, kc, KZ, sc, PITCH, A.rows, &vtab[tid]);
+            view_record(A.M + 12 * (size_t)s, i0, j0, ni, nj, kc, KZ, sc, PITCH, A.rows, true,
+                        &vtab[tid]);
         }
         __syncthreads();
         for (int qv = 0; qv < nb; ++qv) {
             const ViewRec& rv = vtab[qv];
-            const int c0 = uniform(rv.c0), r0 = uniform(rv.r0);
-            const int C = uniform(rv.C), R = uniform(rv.R);
+            const int c0 = uniform(rv.c0), C = uniform(rv.C);
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(proj + (size_t)(sb + qv) * view_bytes), 0, (int)view_bytes, kBufferFlags);
             // ---- stage the footprint of view sb+qv (zero outside the detector)
-            stage_view<PITCH, F16>(tile, proj + (size_t)(sb + qv) * view_bytes, A.nh, A.nw, r0, c0,
-                                   R, C, wave, lane);
+            stage_rows<PITCH, F16>(tile, rs, A.nh, row_bytes, A.nw, uniform(rv.r0), c0,
+                                   uniform(rv.R), C, wave, lane);
             __builtin_amdgcn_s_waitcnt(0);                    // this wave's LDS writes landed
             __syncthreads();
             // ---- hoisted per (column, view) quantities
@@ -178,31 +250,26 @@ __global__ __launch_bounds__(kThreads) void bp_kernel(const BpArgs A)
             float F = __builtin_amdgcn_rcpf(w);
             F = F * fmaf(-w, F, 2.0f);                        // one Newton step
             const float u = fmaf(uniform(rv.a), di, fmaf(uniform(rv.b), dj, uniform(rv.N0))) * F;
-            const float v0 = fmaf(uniform(rv.g), di, fmaf(uniform(rv.h), dj, uniform(rv.V0))) * F;
             const float dv = uniform(rv.m12) * F;
             const float W = F * F * uniform(rv.scale);
             const float fu = __builtin_amdgcn_fractf(u);
-            // LDS byte address of column floor(u) of row 0 (u >= 1 inside the tile)
+            // LDS byte address of column floor(u) of tile row 0 (u >= 1 inside the tile)
             const unsigned base = tile_base + 4u * (unsigned)(int)u;
-            // ---- hot loop: KZ updates of this column for this view
+            // ---- hot loop: KZ updates of this column for this view, in two
+            // halves; a footprint taller than the LDS tile is staged per half
 #pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const float v = fmaf((float)kk, dv, v0);
-                const float fv = __builtin_amdgcn_fractf(v);
-                // row floor(v) (v >= 1 inside the tile): one 24-bit multiply-add
-                const unsigned at = __umul24((unsigned)(int)v, 4u * PITCH) + base;
-                float h0, h1;
-                if (F16) {
-                    const lds_u32* p = (const lds_u32*)(size_t)at;
-                    h0 = lerp_pair_f16(p[0], fu);
-                    h1 = lerp_pair_f16(p[PITCH], fu);
-                } else {
-                    const lds_f32* p = (const lds_f32*)(size_t)at;
-                    const float p00 = p[0], p01 = p[1], p10 = p[PITCH], p11 = p[PITCH + 1];
-                    h0 = fmaf(fu, p01 - p00, p00);
-                    h1 = fmaf(fu, p11 - p10, p10);
+            for (int q = 0; q < 2; ++q) {
+                if (q == 1 && uniform(rv.split)) {
+                    __syncthreads();
+                    stage_rows<PITCH, F16>(tile, rs, A.nh, row_bytes, A.nw, uniform(rv.r1), c0,
+                                           uniform(rv.R1), C, wave, lane);
+                    __builtin_amdgcn_s_waitcnt(0);
+                    __syncthreads();
                 }
-                acc[kk] = fmaf(W, fmaf(fv, h1 - h0, h0), acc[kk]);
+                const HalfBase& hb = rv.half[q];
+                const float v0 = fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
+                const unsigned row_base = base + (unsigned)(uniform(hb.row) * 4 * PITCH);
+                update_half<KZ, PITCH, F16>(acc, q * (KZ / 2), row_base, v0, dv, fu, W);
             }
             __syncthreads();                                  // tile is overwritten next
         }
@@ -242,13 +309,13 @@ template <int KZ>
 fdk_status launch_kz(const BpArgs& a, int pitch, bool f16, size_t lds, unsigned blocks, hipStream_t st)
 {
     switch (pitch) {
-        case 48: return launch_kz_pitch<KZ, 48>(a, f16, lds, blocks, st);
-        case 80: return launch_kz_pitch<KZ, 80>(a, f16, lds, blocks, st);
-        case 112: return launch_kz_pitch<KZ, 112>(a, f16, lds, blocks, st);
-        case 144: return launch_kz_pitch<KZ, 144>(a, f16, lds, blocks, st);
-        case 176: return launch_kz_pitch<KZ, 176>(a, f16, lds, blocks, st);
-        case 208: return launch_kz_pitch<KZ, 208>(a, f16, lds, blocks, st);
-        case 240: return launch_kz_pitch<KZ, 240>(a, f16, lds, blocks, st);
+        case 40: return launch_kz_pitch<KZ, 40>(a, f16, lds, blocks, st);
+        case 56: return launch_kz_pitch<KZ, 56>(a, f16, lds, blocks, st);
+        case 72: return launch_kz_pitch<KZ, 72>(a, f16, lds, blocks, st);
+        case 88: return launch_kz_pitch<KZ, 88>(a, f16, lds, blocks, st);
+        case 120: return launch_kz_pitch<KZ, 120>(a, f16, lds, blocks, st);
+        case 184: return launch_kz_pitch<KZ, 184>(a, f16, lds, blocks, st);
+        case 248: return launch_kz_pitch<KZ, 248>(a, f16, lds, blocks, st);
     }
     return fail(FDK_E_UNSUPPORTED, "no kernel for this LDS pitch");
 }

@@ -8,69 +8,123 @@
 
 namespace fdk {
 
-// Per (block, view) record in LDS, 16 words.
+// Per (block, view) record in LDS, 24 words.  The slices of a chunk are
+// processed in two halves; each half has its own row origin so that its FP32
+// row coordinates stay below the height of half a footprint.
+struct HalfBase {
+    float g, h, V0;           // v_loc w = V0 + g di + h dj + m12 t, t = slice - first slice of the half
+    int row;                  // LDS tile row of the half's origin
+};
 struct ViewRec {
-    int c0, r0, C, R;         // staged footprint: columns [c0, c0+C), rows [r0, r0+R)
+    int c0, C;                // staged columns [c0, c0 + C)
+    int r0, R;                // rows [r0, r0 + R) staged first
     float d, e, w0;           // w  = w0 + d di + e dj
     float a, b, N0;           // u_loc w = N0 + a di + b dj   (u_loc = u - c0)
-    float g, h, V0;           // v_loc w = V0 + g di + h dj + m12 kk (v_loc = v - r0)
+    HalfBase half[2];
     float m12;
     float scale;              // dequantisation scale of the view (1 for float32)
-    float invC;               // 1 / C, for the staging index split
+    int split;                // 1: the second half's rows [r1, r1 + R1) are staged separately
+    int r1, R1;
+    int pad;
 };
-static_assert(sizeof(ViewRec) == 16 * 4, "view record is 16 words");
+static_assert(sizeof(ViewRec) == 24 * 4, "view record is 24 words");
 
-// FP64 bases of one view for one block.  Footprint from the four corner
-// columns of the tile and the two end slices of the chunk (the projective
-// image of the voxel box is the hull of its corner images), with one pixel of
-// margin on each side for FP32 rounding of the per-thread coordinates.
-__device__ inline void view_record(const double* __restrict__ m, int i0, int j0, int ni, int nj, int kc,
-                            int kz, float scale, int pitch_max, int rows_max, ViewRec* out)
+// The corner loops below are kept rolled: this FP64 code runs once per view
+// and block, and unrolling it would raise the register count of the whole
+// kernel (and so lower its occupancy).
+//
+// Rows [first, first + count) that slices ka..kb of the tile reach: the
+// projective image of the voxel box is the hull of its corner images, so the
+// four corner columns at the two end slices bound it; one row of margin on
+// each side absorbs FP32 rounding of the per-thread coordinates.
+__device__ inline void footprint_rows(const double* __restrict__ m, const double* ii,
+                                      const double* jj, double ka, double kb, int* first, int* count)
 {
-    const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
-    const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
-    double umin = 1e300, umax = -1e300, vmin = 1e300, vmax = -1e300;
-#pragma unroll
+    double vmin = 1e300, vmax = -1e300;
+#pragma unroll 1
     for (int a = 0; a < 2; ++a)
-#pragma unroll
+#pragma unroll 1
         for (int b = 0; b < 2; ++b) {
-            const double w = m[8] * ii[a] + m[9] * jj[b] + m[11];
-            const double rw = 1.0 / w;
-            const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) * rw;
+            const double rw = 1.0 / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
             const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
-            const double v0 = (A + m[6] * (double)kc) * rw;
-            const double v1 = (A + m[6] * (double)(kc + kz - 1)) * rw;
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
+            const double v0 = (A + m[6] * ka) * rw;
+            const double v1 = (A + m[6] * kb) * rw;
             vmin = fmin(vmin, fmin(v0, v1));
             vmax = fmax(vmax, fmax(v0, v1));
         }
-    const double fu0 = floor(umin), fu1 = floor(umax), fv0 = floor(vmin), fv1 = floor(vmax);
+    const double f0 = floor(vmin), f1 = floor(vmax);
+    *first = (int)f0 - 1;
+    *count = (int)(f1 - f0) + 4;
+}
+
+// FP64 bases of one view for one block (tile origin (i0, j0), ni x nj real
+// columns, slices kc .. kc + kz - 1).  The window is the footprint of the
+// whole chunk when it has at most rows_max rows (or `allow_split` is false);
+// otherwise the first half's rows are staged first and the second half's
+// separately (each half fits rows_max by construction of the launch plan).
+__device__ inline void view_record(const double* __restrict__ m, int i0, int j0, int ni, int nj,
+                                   int kc, int kz, float scale, int pitch_max, int rows_max,
+                                   bool allow_split, ViewRec* out)
+{
+    const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
+    const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
+    double umin = 1e300, umax = -1e300;
+#pragma unroll 1
+    for (int a = 0; a < 2; ++a)
+#pragma unroll 1
+        for (int b = 0; b < 2; ++b) {
+            const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+    const double fu0 = floor(umin), fu1 = floor(umax);
     const int c0 = (int)fu0 - 1;
-    const int r0 = (int)fv0 - 1;
     int C = (int)(fu1 - fu0) + 4;
-    int R = (int)(fv1 - fv0) + 4;
-    C = C < pitch_max ? C : pitch_max;     // the launch plan bounds both; clamp for safety
-    R = R < rows_max ? R : rows_max;
+    C = C < pitch_max ? C : pitch_max;     // the launch plan bounds C; clamp for safety
+    const int h2 = kz / 2;
+    int rf, Rf, ra, Ra, rb, Rb;
+    footprint_rows(m, ii, jj, (double)kc, (double)(kc + kz - 1), &rf, &Rf);
+    footprint_rows(m, ii, jj, (double)kc, (double)(kc + h2 - 1), &ra, &Ra);
+    footprint_rows(m, ii, jj, (double)(kc + h2), (double)(kc + kz - 1), &rb, &Rb);
+    const bool split = Rf > rows_max && allow_split;
     const double w0 = m[8] * i0 + m[9] * j0 + m[11];
     out->c0 = c0;
-    out->r0 = r0;
     out->C = C;
-    out->R = R;
     out->d = (float)m[8];
     out->e = (float)m[9];
     out->w0 = (float)w0;
     out->a = (float)(m[0] - c0 * m[8]);
     out->b = (float)(m[1] - c0 * m[9]);
     out->N0 = (float)((m[0] * i0 + m[1] * j0 + m[3]) - c0 * w0);
-    out->g = (float)(m[4] - r0 * m[8]);
-    out->h = (float)(m[5] - r0 * m[9]);
-    out->V0 = (float)((m[4] * i0 + m[5] * j0 + m[6] * (double)kc + m[7]) - r0 * w0);
+    const int org[2] = {ra, rb};
+    const int ks[2] = {kc, kc + h2};
+    for (int q = 0; q < 2; ++q) {
+        out->half[q].g = (float)(m[4] - org[q] * m[8]);
+        out->half[q].h = (float)(m[5] - org[q] * m[9]);
+        out->half[q].V0 = (float)((m[4] * i0 + m[5] * j0 + m[6] * (double)ks[q] + m[7]) - org[q] * w0);
+    }
+    if (split) {
+        out->r0 = ra;
+        out->R = Ra < rows_max ? Ra : rows_max;
+        out->half[0].row = 0;
+        out->half[1].row = 0;
+        out->split = 1;
+        out->r1 = rb;
+        out->R1 = Rb < rows_max ? Rb : rows_max;
+    } else {
+        // both halves' windows lie inside the whole-chunk window
+        out->r0 = rf;
+        out->R = Rf < rows_max ? Rf : rows_max;
+        out->half[0].row = ra - rf;
+        out->half[1].row = rb - rf;
+        out->split = 0;
+        out->r1 = rb;
+        out->R1 = 0;
+    }
     out->m12 = (float)m[6];
     out->scale = scale;
-    out->invC = 1.0f / (float)C;
+    out->pad = 0;
 }
-
 
 // Block id -> (chunk, tile).  Chunk-major so that resident blocks cover a thin
 // z-slab; blocks are dealt to the 8 XCDs round-robin by id, so XCD x gets the

@@ -41,6 +41,7 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const FpArgs A)
     const int i0 = tx * kTile, j0 = ty * kTile;
     const int ni = min(kTile, A.nx - i0), nj = min(kTile, A.ny - j0);
     const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int lx = tid & (kTile - 1), ly = tid >> 4;
     const bool active = lx < ni && ly < nj;
     const float di = (float)min(lx, ni - 1), dj = (float)min(ly, nj - 1);
@@ -59,45 +60,49 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const FpArgs A)
         __syncthreads();
         if (tid < nb)
             view_record(A.M + 12 * (size_t)(sb + tid), i0, j0, ni, nj, kc, KZ, 1.0f, PITCH, A.rows,
-                        &vtab[tid]);
+                        false, &vtab[tid]);
         __syncthreads();
         for (int qv = 0; qv < nb; ++qv) {
             const ViewRec rec = vtab[qv];
-            const int n = rec.R * rec.C;
-            for (int t = tid; t < n; t += kThreads) {
-                const int rr = (int)(((float)t + 0.5f) * rec.invC);
-                tile[rr * PITCH + (t - rr * rec.C)] = 0.f;
-            }
+            // rows of the window to waves, columns to lanes
+            for (int rr = wave; rr < rec.R; rr += kThreads / 64)
+                for (int cc = lane; cc < rec.C; cc += 64) tile[rr * PITCH + cc] = 0.f;
             __syncthreads();
             const float w = fmaf(rec.d, di, fmaf(rec.e, dj, rec.w0));
             const float F = 1.0f / w;
             const float u = fmaf(rec.a, di, fmaf(rec.b, dj, rec.N0)) * F;
-            const float v0 = fmaf(rec.g, di, fmaf(rec.h, dj, rec.V0)) * F;
             const float dv = rec.m12 * F;
             const float W = F * F;
             const float fu = __builtin_amdgcn_fractf(u);
             float* T0 = tile + (int)u;
 #pragma unroll
-            for (int kk = 0; kk < KZ; ++kk) {
-                const float v = fmaf((float)kk, dv, v0);
-                const float fv = __builtin_amdgcn_fractf(v);
-                float* p = T0 + (int)v * PITCH;
-                const float xw = x[kk] * W;
-                const float lo = xw * (1.0f - fv), hi = xw * fv;
-                unsafeAtomicAdd(p, lo * (1.0f - fu));
-                unsafeAtomicAdd(p + 1, lo * fu);
-                unsafeAtomicAdd(p + PITCH, hi * (1.0f - fu));
-                unsafeAtomicAdd(p + PITCH + 1, hi * fu);
+            for (int q = 0; q < 2; ++q) {
+                const float v0 = fmaf(rec.half[q].g, di, fmaf(rec.half[q].h, dj, rec.half[q].V0)) * F;
+                float* Tq = T0 + rec.half[q].row * PITCH;
+#pragma unroll
+                for (int t = 0; t < KZ / 2; ++t) {
+                    const float v = fmaf((float)t, dv, v0);
+                    const float fv = __builtin_amdgcn_fractf(v);
+                    float* p = Tq + (int)v * PITCH;
+                    const float xw = x[q * (KZ / 2) + t] * W;
+                    const float lo = xw * (1.0f - fv), hi = xw * fv;
+                    unsafeAtomicAdd(p, lo * (1.0f - fu));
+                    unsafeAtomicAdd(p + 1, lo * fu);
+                    unsafeAtomicAdd(p + PITCH, hi * (1.0f - fu));
+                    unsafeAtomicAdd(p + PITCH + 1, hi * fu);
+                }
             }
             __syncthreads();
             float* dst = A.proj + (size_t)(sb + qv) * view_px;
-            for (int t = tid; t < n; t += kThreads) {
-                const int rr = (int)(((float)t + 0.5f) * rec.invC);
-                const int cc = t - rr * rec.C;
-                const int r = rec.r0 + rr, c = rec.c0 + cc;
-                const float val = tile[rr * PITCH + cc];
-                if (val != 0.f && (unsigned)r < (unsigned)A.nh && (unsigned)c < (unsigned)A.nw)
-                    unsafeAtomicAdd(dst + (size_t)r * A.nw + c, val);
+            for (int rr = wave; rr < rec.R; rr += kThreads / 64) {
+                const int r = rec.r0 + rr;
+                if ((unsigned)r >= (unsigned)A.nh) continue;
+                for (int cc = lane; cc < rec.C; cc += 64) {
+                    const int c = rec.c0 + cc;
+                    const float val = tile[rr * PITCH + cc];
+                    if (val != 0.f && (unsigned)c < (unsigned)A.nw)
+                        unsafeAtomicAdd(dst + (size_t)r * A.nw + c, val);
+                }
             }
             __syncthreads();
         }
@@ -120,13 +125,13 @@ template <int KZ>
 fdk_status launch_fp_k(const FpArgs& a, int pitch, size_t lds, unsigned blocks, hipStream_t st)
 {
     switch (pitch) {
-        case 48: return launch_fp_kp<KZ, 48>(a, lds, blocks, st);
-        case 80: return launch_fp_kp<KZ, 80>(a, lds, blocks, st);
-        case 112: return launch_fp_kp<KZ, 112>(a, lds, blocks, st);
-        case 144: return launch_fp_kp<KZ, 144>(a, lds, blocks, st);
-        case 176: return launch_fp_kp<KZ, 176>(a, lds, blocks, st);
-        case 208: return launch_fp_kp<KZ, 208>(a, lds, blocks, st);
-        case 240: return launch_fp_kp<KZ, 240>(a, lds, blocks, st);
+        case 40: return launch_fp_kp<KZ, 40>(a, lds, blocks, st);
+        case 56: return launch_fp_kp<KZ, 56>(a, lds, blocks, st);
+        case 72: return launch_fp_kp<KZ, 72>(a, lds, blocks, st);
+        case 88: return launch_fp_kp<KZ, 88>(a, lds, blocks, st);
+        case 120: return launch_fp_kp<KZ, 120>(a, lds, blocks, st);
+        case 184: return launch_fp_kp<KZ, 184>(a, lds, blocks, st);
+        case 248: return launch_fp_kp<KZ, 248>(a, lds, blocks, st);
     }
     return fail(FDK_E_UNSUPPORTED, "no kernel for this LDS pitch");
 }
@@ -147,10 +152,11 @@ fdk_status launch_forwardproject(const FpLaunch& a, const BpPlan& plan, void* st
     A.ntx = plan.ntx;
     A.ntiles = plan.ntx * plan.nty;
     A.ntiles_pad = plan.ntiles_pad;
-    A.rows = plan.rows;
+    A.rows = plan.rows_full;
     const int64_t blocks = (int64_t)plan.ntiles_pad * plan.nchunks;
     if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "grid too large");
-    const size_t lds = (size_t)plan.lds_bytes;
+    const size_t lds = (size_t)plan.fp_lds_bytes;
+    if (lds > 160 * 1024) return fail(FDK_E_UNSUPPORTED, "forward-projection footprint exceeds LDS");
     switch (plan.kz) {
         case 8: return launch_fp_k<8>(A, plan.pitch, lds, (unsigned)blocks, st);
         case 16: return launch_fp_k<16>(A, plan.pitch, lds, (unsigned)blocks, st);

@@ -113,32 +113,51 @@ fdk_status validate_geometry(const fdk_volume& vg, const fdk_stack& sg, const do
 
 // ------------------------------------------------------------------ plan
 
-const int kPitches[] = {48, 80, 112, 144, 176, 208, 240};
+const int kPitches[] = {40, 56, 72, 88, 120, 184, 248};
 const int kNumPitches = (int)(sizeof(kPitches) / sizeof(kPitches[0]));
 
 namespace {
 
 struct Extent {
-    int cols = 0;   // max over blocks/views of floor(umax) - floor(umin) + 4
-    int rows = 0;   // upper bound of floor(vmax) - floor(vmin) + 4 over blocks/views
+    int cols = 0;        // max over blocks/views of floor(umax) - floor(umin) + 4
+    int rows_full = 0;   // bound of the rows of a whole chunk of slices
+    int rows_half = 0;   // bound of the rows of half a chunk
+    int rows_p95 = 0;    // 95th percentile of the whole-chunk rows
 };
 
-// Footprint of every (xy tile, view) for a given number of slices per block.
-// The kernel computes, per block and view, from the four corner columns of its
-// tile and the two end slices of its chunk:
-//   cols = floor(umax) - floor(umin) + 4,  rows = floor(vmax) - floor(vmin) + 4.
-// The width does not depend on the chunk.  The height of a chunk is a convex
-// function of the chunk start (max of affine minus min of affine), so its
-// maximum is at the first or the last chunk; floor(a) - floor(b) <=
-// floor(a - b) + 1 bounds the floors.
+// Rows a set of slices needs, as the kernel computes it (four corner columns
+// of the tile at the two end slices): floor(vmax) - floor(vmin) + 4.
+inline int rows_of(const double* m, const double* ii, const double* jj, const double* rw,
+                   double ka, double kb)
+{
+    double lo = 1e300, hi = -1e300;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
+            const double v0 = (A + m[6] * ka) * rw[2 * a + b];
+            const double v1 = (A + m[6] * kb) * rw[2 * a + b];
+            lo = std::min(lo, std::min(v0, v1));
+            hi = std::max(hi, std::max(v0, v1));
+        }
+    return (int)(std::floor(hi) - std::floor(lo)) + 4;
+}
+
+// Footprints of every (xy tile, view) for a given number of slices per block,
+// following the kernel's rule.  The width does not depend on the chunk.  The
+// height of a set of slices is a convex function of the chunk start (max of
+// affine functions minus min of affine functions), so its maximum over all
+// chunks is at the first or the last chunk; the floors add at most 1 to
+// floor(vmax - vmin) + 4 in between, and one more row/column covers
+// host/device rounding.
 Extent footprint(const fdk_volume& vg, const std::vector<IndexMatrix>& M, int kz)
 {
     Extent e;
     const int ntx = (vg.nx + kTile - 1) / kTile, nty = (vg.ny + kTile - 1) / kTile;
     const int nch = (vg.nz + kz - 1) / kz;
-    const double kA[2] = {0.0, (double)((nch - 1) * kz)};
-    double umax_ext = 0, vmax_ext = 0;
-    int cols = 0;
+    const double kfirst = 0.0, kmid = (double)((nch / 2) * kz), klast = (double)((nch - 1) * kz);
+    std::vector<int> hist(4096, 0);
+    int cols = 0, rf = 0, rh = 0;
+    int64_t count = 0;
     for (size_t s = 0; s < M.size(); ++s) {
         const double* m = M[s].m;
         for (int ty = 0; ty < nty; ++ty) {
@@ -147,32 +166,39 @@ Extent footprint(const fdk_volume& vg, const std::vector<IndexMatrix>& M, int kz
             for (int tx = 0; tx < ntx; ++tx) {
                 const int i0 = tx * kTile, ni = std::min(kTile, vg.nx - i0);
                 const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
-                double umin = 1e300, umax = -1e300;
-                double vlo[2] = {1e300, 1e300}, vhi[2] = {-1e300, -1e300};
+                double umin = 1e300, umax = -1e300, rw[4];
                 for (int a = 0; a < 2; ++a)
                     for (int b = 0; b < 2; ++b) {
                         const double w = m[8] * ii[a] + m[9] * jj[b] + m[11];
-                        const double rw = 1.0 / w;
-                        const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) * rw;
+                        rw[2 * a + b] = 1.0 / w;
+                        const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / w;
                         umin = std::min(umin, u);
                         umax = std::max(umax, u);
-                        const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
-                        for (int c = 0; c < 2; ++c) {
-                            const double v0 = (A + m[6] * kA[c]) * rw;
-                            const double v1 = (A + m[6] * (kA[c] + kz - 1)) * rw;
-                            vlo[c] = std::min(vlo[c], std::min(v0, v1));
-                            vhi[c] = std::max(vhi[c], std::max(v0, v1));
-                        }
                     }
                 cols = std::max(cols, (int)(std::floor(umax) - std::floor(umin)) + 4);
-                umax_ext = std::max(umax_ext, umax - umin);
-                for (int c = 0; c < 2; ++c) vmax_ext = std::max(vmax_ext, vhi[c] - vlo[c]);
+                for (double k0 : {kfirst, klast}) {
+                    rf = std::max(rf, rows_of(m, ii, jj, rw, k0, k0 + kz - 1));
+                    rh = std::max(rh, rows_of(m, ii, jj, rw, k0, k0 + kz / 2 - 1));
+                    rh = std::max(rh, rows_of(m, ii, jj, rw, k0 + kz / 2, k0 + kz - 1));
+                }
+                for (double k0 : {kfirst, kmid, klast}) {
+                    const int r = rows_of(m, ii, jj, rw, k0, k0 + kz - 1);
+                    hist[std::min(r, 4095)]++;
+                    count++;
+                }
             }
         }
     }
-    (void)umax_ext;
-    e.cols = cols + 1;                                       // host/device rounding slack
-    e.rows = (int)std::floor(vmax_ext) + 1 + 4 + 1;
+    int64_t acc = 0;
+    int p95 = 0;
+    for (int r = 0; r < 4096; ++r) {
+        acc += hist[r];
+        if (acc * 100 >= count * 95) { p95 = r; break; }
+    }
+    e.cols = cols + 1;
+    e.rows_full = rf + 2;
+    e.rows_half = rh + 2;
+    e.rows_p95 = p95 + 1;
     return e;
 }
 
@@ -202,7 +228,7 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
                         const std::vector<IndexMatrix>& M, BpPlan& plan)
 {
     const int kz_force = env_int("FDK_BP_KZ", 0);
-    const int lds_budget = env_int("FDK_BP_LDS_BUDGET", 48 * 1024);
+    const int lds_budget = env_int("FDK_BP_LDS_BUDGET", 32 * 1024);
     uint64_t h = 1469598103934665603ull;
     h = fnv1a(h, &vg.nx, sizeof(int32_t) * 3);
     h = fnv1a(h, &sg.np, sizeof(int32_t) * 3);
@@ -218,11 +244,15 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
                 return FDK_OK;
             }
     }
+    // LDS rows: enough for every half-chunk and for 95% of the whole-chunk
+    // footprints (taller ones are processed per half-chunk).  Largest slice
+    // count whose tile fits the budget; otherwise the smallest tile.
     const int cands[3] = {32, 16, 8};
     const int table_bytes = kViewBatch * kViewRec * 4;
     BpPlan best;
     bool found = false;
-    for (int q = 0; q < 3 && !found; ++q) {
+    int64_t best_bytes = 0;
+    for (int q = 0; q < 3; ++q) {
         const int kz = cands[q];
         if (kz_force && kz != kz_force) continue;
         Extent e = footprint(vg, M, kz);
@@ -230,16 +260,22 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
         for (int p = 0; p < kNumPitches; ++p)
             if (kPitches[p] >= e.cols) { pitch = kPitches[p]; break; }
         if (!pitch) continue;
-        const int64_t bytes = (int64_t)e.rows * pitch * 4 + table_bytes;
-        const bool last = (q == 2) || (kz_force == kz);
-        if (bytes <= lds_budget || (last && bytes <= 150 * 1024) || (kz_force == kz && bytes <= 150 * 1024)) {
+        const int rows = std::max(e.rows_half, std::min(e.rows_p95, e.rows_full));
+        const int64_t bytes = (int64_t)rows * pitch * 4 + table_bytes;
+        const int64_t fp_bytes = (int64_t)e.rows_full * pitch * 4 + table_bytes;
+        if (bytes > 150 * 1024) continue;
+        if (!found || (best_bytes > lds_budget && bytes < best_bytes)) {
             best.kz = kz;
             best.pitch = pitch;
-            best.rows = e.rows;
+            best.rows = rows;
+            best.rows_full = e.rows_full;
             best.cols = e.cols;
             best.lds_bytes = bytes;
+            best.fp_lds_bytes = fp_bytes;
+            best_bytes = bytes;
             found = true;
         }
+        if (found && best_bytes <= lds_budget) break;
     }
     if (!found)
         return fail(FDK_E_UNSUPPORTED,

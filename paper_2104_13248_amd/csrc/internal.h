@@ -35,16 +35,18 @@ fdk_status validate_geometry(const fdk_volume& vg, const fdk_stack& sg, const do
 // ---------------------------------------------------------------- BP plan
 constexpr int kTile = 16;            // columns per block along x and along y
 constexpr int kThreads = kTile * kTile;
-constexpr int kViewBatch = 64;       // views whose per-block constants are built at once
-constexpr int kViewRec = 16;         // 32-bit words per view record in LDS
+constexpr int kViewBatch = 32;       // views whose per-block constants are built at once
+constexpr int kViewRec = 24;         // 32-bit words per view record in LDS
 
 struct BpPlan {
     int kz = 0;          // slices per thread (register accumulators)
     int pitch = 0;       // LDS row pitch in floats (compile-time in the kernel)
-    int rows = 0;        // LDS rows (maximum footprint height over all blocks/views)
+    int rows = 0;        // LDS rows of the back-projector (taller footprints are split)
+    int rows_full = 0;   // bound of every whole-chunk footprint height
     int cols = 0;        // maximum footprint width
     int ntx = 0, nty = 0, ntiles_pad = 0, nchunks = 0;
-    int64_t lds_bytes = 0;
+    int64_t lds_bytes = 0;      // back-projector LDS per block
+    int64_t fp_lds_bytes = 0;   // forward projector LDS per block (no splitting)
     int64_t blocks = 0;
 };
 

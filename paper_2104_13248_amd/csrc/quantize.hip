@@ -24,18 +24,36 @@ __global__ void clear_u32(unsigned* p, int n)
     if (i < n) p[i] = 0u;
 }
 
+// Per-view absolute maximum: a few blocks per view stream the view with
+// 16-byte loads (scalar loads for an unaligned view or the tail), reduce in
+// the wave and across the block, and post one atomicMax per block.
 __global__ __launch_bounds__(kQThreads) void absmax_kernel(const float* __restrict__ in, int64_t npix,
                                                            unsigned* __restrict__ maxbits)
 {
+    __shared__ float part[kQThreads / 64];
     const int s = blockIdx.y;
     const float* p = in + (size_t)s * npix;
+    const int64_t nthreads = (int64_t)gridDim.x * kQThreads;
+    const int64_t t0 = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
     float m = 0.f;
-    for (int64_t t = (int64_t)blockIdx.x * kQThreads + threadIdx.x; t < npix;
-         t += (int64_t)gridDim.x * kQThreads)
-        m = fmaxf(m, fabsf(p[t]));
-    // wave reduction, then one atomic per wave
+    int64_t head = 0;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+        const int64_t n4 = npix / 4;
+        for (int64_t t = t0; t < n4; t += nthreads) {
+            const float4 x = p4[t];
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+        }
+        head = n4 * 4;
+    }
+    for (int64_t t = head + t0; t < npix; t += nthreads) m = fmaxf(m, fabsf(p[t]));
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(&maxbits[s], __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kQThreads / 64; ++w) m = fmaxf(m, part[w]);
+        atomicMax(&maxbits[s], __float_as_uint(m));          // m >= 0: bit order = value order
+    }
 }
 
 __device__ __forceinline__ float view_scale(float m)
@@ -76,11 +94,15 @@ fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16
     unsigned* mx = (unsigned*)d_max;
     hipLaunchKernelGGL(clear_u32, dim3((np + 255) / 256), dim3(256), 0, st, mx, np);
     s = check_launch("clear kernel");
+    // enough blocks to fill the GPU, each streaming a large contiguous share
+    int64_t bmax = (npix + kQThreads * 16 - 1) / (kQThreads * 16);
+    if (bmax < 1) bmax = 1;
+    const int64_t bm = bmax < 16 ? bmax : 16;
     int64_t bx = (npix + kQThreads * 8 - 1) / (kQThreads * 8);
     if (bx > 1024) bx = 1024;
     if (bx < 1) bx = 1;
     if (s == FDK_OK) {
-        hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)bx, (unsigned)np), dim3(kQThreads), 0, st,
+        hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)bm, (unsigned)np), dim3(kQThreads), 0, st,
                            in, npix, mx);
         s = check_launch("absmax kernel");
     }

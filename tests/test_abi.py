@@ -119,7 +119,7 @@ def test_tilted_detector_rejected():
     m3 = m.copy()
     m3[0, 0, 2] = 1e-16                      # round-off sized entries are accepted
     vg2 = _lib.volume_struct(C1["shape"], C1["voxel"])
-    out = (ctypes.c_int64 * 8)()
+    out = (ctypes.c_int64 * 10)()
     assert _lib.lib.fdk_bp_plan(ctypes.byref(vg2), ctypes.byref(sg), _lib.ptr(m3),
                                 ctypes.cast(out, ctypes.c_void_p)) == OK
 
@@ -194,9 +194,10 @@ def test_circular_matrices_match_ray_plane_geometry():
 
 @pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
 def test_plan_covers_every_footprint(name):
-    """The launch plan's LDS window bounds the footprint of every block and
-    view (checked here by brute force over all tiles, chunks and views, in
-    FP64, with the kernel's own footprint rule)."""
+    """The launch plan bounds the footprint of every block and view (checked
+    here by brute force over tiles, chunks and views, in FP64, with the
+    kernel's own rule): every half-chunk fits the LDS rows, every whole chunk
+    fits rows_full, every width fits the pitch."""
     cfg = wl.CONFIGS[name]
     m = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
     plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], cfg["np"], cfg["nh"], cfg["nw"], m)
@@ -210,22 +211,28 @@ def test_plan_covers_every_footprint(name):
     k0 = np.arange(0, nz, kz)
     I = np.stack([i0, np.minimum(i0 + 15, nx - 1)], 1)          # [ntx, 2]
     J = np.stack([j0, np.minimum(j0 + 15, ny - 1)], 1)
-    cols = rows = 0
+
+    def rows(A, w, ka, kb, Ms):
+        v0 = (A + Ms[1, 2] * ka) / w
+        v1 = (A + Ms[1, 2] * kb) / w
+        vmin = np.minimum(v0, v1).min(axis=(2, 3))
+        vmax = np.maximum(v0, v1).max(axis=(2, 3))
+        return int((np.floor(vmax) - np.floor(vmin)).max()) + 4
+
+    cols = full = half = 0
     for Ms in M:
         ii = I[:, None, :, None]
         jj = J[None, :, None, :]
         w = Ms[2, 0] * ii + Ms[2, 1] * jj + Ms[2, 3]
         u = (Ms[0, 0] * ii + Ms[0, 1] * jj + Ms[0, 3]) / w
-        umin = u.min(axis=(2, 3))
-        umax = u.max(axis=(2, 3))
-        cols = max(cols, int((np.floor(umax) - np.floor(umin)).max()) + 4)
+        cols = max(cols, int((np.floor(u.max(axis=(2, 3))) - np.floor(u.min(axis=(2, 3)))).max()) + 4)
         A = Ms[1, 0] * ii + Ms[1, 1] * jj + Ms[1, 3]
         for kc in k0:
-            v0 = (A + Ms[1, 2] * kc) / w
-            v1 = (A + Ms[1, 2] * (kc + kz - 1)) / w
-            vmin = np.minimum(v0, v1).min(axis=(2, 3))
-            vmax = np.maximum(v0, v1).max(axis=(2, 3))
-            rows = max(rows, int((np.floor(vmax) - np.floor(vmin)).max()) + 4)
+            full = max(full, rows(A, w, kc, kc + kz - 1, Ms))
+            half = max(half, rows(A, w, kc, kc + kz // 2 - 1, Ms),
+                       rows(A, w, kc + kz // 2, kc + kz - 1, Ms))
     assert cols <= plan["lds_pitch"]
-    assert rows <= plan["lds_rows"]
+    assert half <= plan["lds_rows"]
+    assert full <= plan["rows_full"]
     assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4
+    assert plan["fp_lds_bytes"] >= plan["rows_full"] * plan["lds_pitch"] * 4

@@ -180,3 +180,47 @@ def test_c2_full_size_sampled():
     e = rel(got, ref)
     log("c2 sampled rel-L2", e)
     assert e <= TOL32
+
+
+# Strongly magnified cone geometries: some blocks' footprints are taller than
+# the LDS tile and are staged per half-chunk.
+SPLIT = [
+    (dict(sod=120.0, sdd=400.0), (96, 48, 48), (24, 400, 300)),
+    (dict(sod=150.0, sdd=450.0), (64, 40, 40), (24, 320, 256)),
+]
+
+
+@pytest.mark.parametrize("kz", [0, 8, 16, 32])
+@pytest.mark.parametrize("case", range(len(SPLIT)))
+def test_split_footprints(case, kz, monkeypatch):
+    over, shape, (npv, nh, nw) = SPLIT[case]
+    if kz:
+        monkeypatch.setenv("FDK_BP_KZ", str(kz))
+    scan = dict(wl.CONFIGS["c1"]["scan"], theta0=0.1, **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    voxel = (1.0, 1.0, 1.0)
+    plan = fdk.bp_plan(shape, voxel, npv, nh, nw, mats)
+    log("split case", case, "kz", kz, plan)
+    if kz == 0:
+        assert plan["rows_full"] > plan["lds_rows"], "geometry does not exercise the split path"
+    proj = wl.gaussian(400 + case, (npv, nh, nw))
+    ref = oracle.backproject(proj, mats, shape, voxel)
+    got = gpu_bp(proj, mats, shape, voxel)
+    e = rel(got, ref)
+    log("f32 rel-L2", e)
+    assert e <= TOL32
+    h, s = fdk.quantize_f16(torch.from_numpy(proj).cuda())
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, voxel, scale=s)
+    torch.cuda.synchronize()
+    ref16 = oracle.backproject(h.cpu().numpy(), mats, shape, voxel, scale=s.cpu().numpy())
+    e16 = rel(vol.cpu().numpy(), ref16)
+    log("f16 rel-L2 vs dequantised", e16)
+    assert e16 <= TOL32
+    # slabs stay bitwise equal to the full volume where footprints are split
+    p = torch.from_numpy(proj).cuda()
+    for k0, kc in [(3, 41), (50, shape[0] - 50)]:
+        slab = torch.zeros((kc,) + shape[1:], dtype=torch.float32, device="cuda")
+        fdk.backproject_slab(slab, shape, k0, p, mats, voxel)
+        torch.cuda.synchronize()
+        assert np.array_equal(slab.cpu().numpy().view(np.uint32), got[k0:k0 + kc].view(np.uint32))

@@ -1,0 +1,142 @@
+"""Parity of the forward projector, the FDK filter and the analytic phantom
+projector with the FP64 oracle, and the end-to-end FDK pipeline (MI355X)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import geometry as og
+from oracle import phantom as oph
+import workloads as wl
+from helpers import c1_filtered, log, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+fdk = pytest.importorskip("paper_2104_13248_amd")
+
+TOL32 = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def gpu_fp(vol, mats, nh, nw, voxel, centre=(0.0, 0.0, 0.0), proj0=None):
+    v = torch.from_numpy(np.ascontiguousarray(vol, dtype=np.float32)).cuda()
+    p = torch.zeros((len(mats), nh, nw), dtype=torch.float32, device="cuda") if proj0 is None \
+        else torch.from_numpy(np.ascontiguousarray(proj0, dtype=np.float32)).cuda()
+    fdk.forwardproject(v, p, mats, voxel, centre)
+    torch.cuda.synchronize()
+    return p.cpu().numpy()
+
+
+FP_CASES = [
+    # config, shape, (np, nh, nw), scan overrides, centre
+    ("c1", (64, 64, 64), (64, 128, 128), {}, (0.0, 0.0, 0.0)),
+    ("c1", (9, 21, 17), (37, 50, 70), dict(theta0=0.4, u_off=2.5, v_off=-1.0), (1.0, -2.0, 3.0)),
+    ("c1", (96, 48, 48), (24, 400, 300), dict(sod=120.0, sdd=400.0), (0.0, 0.0, 0.0)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(FP_CASES)))
+def test_forward_projection_parity(case):
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
+    scan = dict(wl.CONFIGS[name]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    x = wl.gaussian(500 + case, shape)
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    e = rel(got, ref)
+    log("fp case", case, "rel-L2", e)
+    assert e <= TOL32
+
+
+def test_forward_projection_accumulates():
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[1]
+    mats = og.scan_matrices(dict(wl.CONFIGS[name]["scan"], **over), npv, nh, nw)
+    x = wl.gaussian(510, shape)
+    base = wl.gaussian(511, (npv, nh, nw))
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre, proj0=base)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0), centre,
+                                proj=base.astype(np.float64))
+    assert rel(got, ref) <= TOL32
+
+
+@pytest.mark.parametrize("case", range(len(FP_CASES)))
+def test_adjoint_identity_on_gpu(case):
+    """<BP p, x> = <p, FP x> with both operators from the HIP library."""
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
+    mats = og.scan_matrices(dict(wl.CONFIGS[name]["scan"], **over), npv, nh, nw)
+    p = wl.gaussian(520 + case, (npv, nh, nw))
+    x = wl.gaussian(530 + case, shape)
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, torch.from_numpy(p).cuda(), mats, (1.0, 1.0, 1.0), centre)
+    fpx = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    bp = vol.cpu().numpy().astype(np.float64)
+    lhs = float(np.sum(bp * x))
+    rhs = float(np.sum(p.astype(np.float64) * fpx))
+    scale = np.linalg.norm(bp) * np.linalg.norm(x)
+    log("adjoint", case, lhs, rhs, abs(lhs - rhs) / scale)
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_filter_parity():
+    cfg = wl.CONFIGS["c1"]
+    ell = wl.config_ellipsoids(cfg, 0)
+    raw = oph.line_integrals(ell, cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"]).astype(np.float32)
+    out = fdk.fdk_filter(torch.from_numpy(raw).cuda(), cfg["scan"])
+    torch.cuda.synchronize()
+    ref = oracle.fdk_filter(raw.astype(np.float64), cfg["scan"])
+    e = rel(out.cpu().numpy(), ref)
+    log("filter rel-L2", e)
+    assert e <= TOL32
+
+
+@pytest.mark.parametrize("nw", [1, 2, 7, 300, 1027])
+def test_filter_ragged_rows(nw):
+    scan = dict(sod=600.0, sdd=1100.0, du=0.8, dv=1.2, arc=2 * math.pi, theta0=0.0,
+                u_off=1.5, v_off=-0.5)
+    raw = wl.gaussian(600 + nw, (3, 5, nw))
+    out = fdk.fdk_filter(torch.from_numpy(raw).cuda(), scan, np_total=360)
+    torch.cuda.synchronize()
+    ref = oracle.fdk_filter(raw.astype(np.float64), scan, np_total=360)
+    assert rel(out.cpu().numpy(), ref) <= TOL32
+
+
+def test_phantom_projector_parity():
+    cfg = wl.CONFIGS["c1"]
+    scan = dict(cfg["scan"], theta0=0.25, u_off=0.5, v_off=-1.5)
+    ell = wl.config_ellipsoids(cfg, 3)
+    views = 16
+    p = torch.zeros((views, cfg["nh"], cfg["nw"]), dtype=torch.float32, device="cuda")
+    fdk.phantom_project(ell, scan, p, view_begin=8, np_total=cfg["np"])
+    torch.cuda.synchronize()
+    ref = oph.line_integrals(ell, scan, cfg["np"], cfg["nh"], cfg["nw"], views=np.arange(8, 8 + views))
+    e = rel(p.cpu().numpy(), ref)
+    log("phantom rel-L2", e)
+    assert e <= 1e-6
+
+
+def test_fdk_pipeline_on_gpu():
+    """GPU phantom -> GPU filter -> GPU back-projection against the oracle
+    pipeline (oracle phantom -> oracle filter -> oracle back-projection)."""
+    cfg = wl.CONFIGS["c1"]
+    scan = cfg["scan"]
+    ell = wl.config_ellipsoids(cfg, 1)
+    raw = torch.zeros((cfg["np"], cfg["nh"], cfg["nw"]), dtype=torch.float32, device="cuda")
+    fdk.phantom_project(ell, scan, raw)
+    filt = fdk.fdk_filter(raw, scan)
+    mats = fdk.scan_matrices(scan, cfg["np"], cfg["nh"], cfg["nw"])
+    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, filt, mats, cfg["voxel"])
+    torch.cuda.synchronize()
+    ref_proj, ref_mats = c1_filtered(1)
+    ref = oracle.backproject(ref_proj, ref_mats, cfg["shape"], cfg["voxel"])
+    e = rel(vol.cpu().numpy(), ref)
+    log("pipeline rel-L2", e)
+    assert e <= 1e-5

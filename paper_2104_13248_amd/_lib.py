@@ -1,4 +1,5 @@
-"""ctypes binding of libfdk.so (include/fdk.h): argument marshalling only.
+"""ctypes binding of libfdk.so (include/fdk.h, include/fdk_learn.h): argument
+marshalling only.
 
 Every operation runs in the HIP kernels of the library; this module checks
 tensor placement, dtype and contiguity, passes raw device pointers and the
@@ -47,6 +48,7 @@ def _load():
     P = ctypes.c_void_p
     I = ctypes.c_int32
     D = ctypes.c_double
+    F = ctypes.c_float
     VP = ctypes.POINTER(Volume)
     SP = ctypes.POINTER(Stack)
     sigs = {
@@ -58,6 +60,13 @@ def _load():
         "fdk_circular_matrices": [I, D, D, D, D, I, I, D, D, D, D, P],
         "fdk_phantom_project": [P, I, SP, P, D, D, D, D, D, D, D, D, I, I, P],
         "fdk_bp_plan": [VP, SP, P, P],
+        # include/fdk_learn.h
+        "fdk_cosine_weight": [SP, P, P, D, D, D, D, D, P],
+        "fdk_conv1d_forward": [I, I, I, I, P, P, P, P, P, F, I, P, P],
+        "fdk_conv1d_backward_data": [I, I, I, I, P, P, P, P, P],
+        "fdk_conv1d_backward_weight": [I, I, I, I, P, P, P, P, P],
+        "fdk_sqerr": [ctypes.c_int64, P, P, P, F, P, P],
+        "fdk_adam": [I, P, P, P, P, F, F, F, F, I, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -72,10 +81,12 @@ def _load():
 
 lib = _load()
 
-#: names declared in include/fdk.h
+#: names declared in include/fdk.h and include/fdk_learn.h
 EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_forwardproject", "fdk_filter",
            "fdk_quantize_f16", "fdk_circular_matrices", "fdk_phantom_project", "fdk_bp_plan",
-           "fdk_last_error", "fdk_status_string")
+           "fdk_last_error", "fdk_status_string",
+           "fdk_cosine_weight", "fdk_conv1d_forward", "fdk_conv1d_backward_data",
+           "fdk_conv1d_backward_weight", "fdk_sqerr", "fdk_adam")
 
 
 def check(code: int) -> None:

@@ -235,3 +235,97 @@ extern "C" fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, cons
     fdk_status s2 = device_free_async(d_ell, stream);
     return s != FDK_OK ? s : s2;
 }
+
+// ---------------------------------------------------------------- learned row filter
+
+#include "fdk_learn.h"
+
+namespace {
+
+fdk_status conv_checks(int32_t cin, int32_t cout, int32_t rows, int32_t len)
+{
+    if (cin <= 0 || cout <= 0 || rows <= 0 || len <= 0)
+        return fail(FDK_E_INVALID, "conv1d sizes must be positive");
+    if ((cin != 1 && cin != 32) || (cout != 1 && cout != 32))
+        return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
+    if ((double)rows * 32.0 * len >= 4.0e18 / 4) return fail(FDK_E_INVALID, "tensor size overflows");
+    return FDK_OK;
+}
+
+}  // namespace
+
+extern "C" fdk_status fdk_cosine_weight(const fdk_stack* sg, const float* raw, float* out,
+                                        double du, double dv, double sdd, double u_off,
+                                        double v_off, void* stream)
+{
+    fdk_status s = validate_stack(sg, false);
+    if (s != FDK_OK) return s;
+    if (!raw || !out) return fail(FDK_E_INVALID, "raw/out pointer is NULL");
+    if (!(du > 0) || !(dv > 0) || !(sdd > 0) || !std::isfinite(du) || !std::isfinite(dv) ||
+        !std::isfinite(sdd) || !std::isfinite(u_off) || !std::isfinite(v_off))
+        return fail(FDK_E_INVALID, "pitches and distances must be positive and finite");
+    FilterLaunch a;
+    a.raw = raw;
+    a.out = out;
+    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+    a.du = du; a.dv = dv; a.sod = sdd; a.sdd = sdd; a.u_off = u_off; a.v_off = v_off;
+    a.arc = 1.0;
+    a.np_total = 1;
+    return launch_cosine_weight(a, stream);
+}
+
+extern "C" fdk_status fdk_conv1d_forward(int32_t cin, int32_t cout, int32_t rows, int32_t len,
+                                         const float* in, const float* w, const float* bias,
+                                         const float* mask, const float* add, float alpha,
+                                         int32_t relu, float* out, void* stream)
+{
+    fdk_status s = conv_checks(cin, cout, rows, len);
+    if (s != FDK_OK) return s;
+    if (!in || !w || !out) return fail(FDK_E_INVALID, "in/w/out pointer is NULL");
+    if (in == out) return fail(FDK_E_INVALID, "in and out must not overlap");
+    if (!std::isfinite(alpha)) return fail(FDK_E_INVALID, "alpha must be finite");
+    return launch_conv1d_forward(cin, cout, rows, len, in, w, bias, mask, add, alpha,
+                                 relu ? 1 : 0, out, stream);
+}
+
+extern "C" fdk_status fdk_conv1d_backward_data(int32_t cin, int32_t cout, int32_t rows,
+                                               int32_t len, const float* gout, const float* w,
+                                               const float* mask, float* gin, void* stream)
+{
+    fdk_status s = conv_checks(cin, cout, rows, len);
+    if (s != FDK_OK) return s;
+    if (!gout || !w || !gin) return fail(FDK_E_INVALID, "gout/w/gin pointer is NULL");
+    if (gout == gin) return fail(FDK_E_INVALID, "gout and gin must not overlap");
+    return launch_conv1d_backward_data(cin, cout, rows, len, gout, w, mask, gin, stream);
+}
+
+extern "C" fdk_status fdk_conv1d_backward_weight(int32_t cin, int32_t cout, int32_t rows,
+                                                 int32_t len, const float* in, const float* gout,
+                                                 float* gw, float* gb, void* stream)
+{
+    fdk_status s = conv_checks(cin, cout, rows, len);
+    if (s != FDK_OK) return s;
+    if (!in || !gout || !gw) return fail(FDK_E_INVALID, "in/gout/gw pointer is NULL");
+    return launch_conv1d_backward_weight(cin, cout, rows, len, in, gout, gw, gb, stream);
+}
+
+extern "C" fdk_status fdk_sqerr(int64_t n, const float* a, const float* b, float* grad,
+                                float grad_scale, float* loss, void* stream)
+{
+    if (n <= 0) return fail(FDK_E_INVALID, "n must be positive");
+    if (!a || !b || !loss) return fail(FDK_E_INVALID, "a/b/loss pointer is NULL");
+    if (!std::isfinite(grad_scale)) return fail(FDK_E_INVALID, "grad_scale must be finite");
+    return launch_sqerr(n, a, b, grad, grad_scale, loss, stream);
+}
+
+extern "C" fdk_status fdk_adam(int32_t n, float* p, const float* g, float* m, float* v, float lr,
+                               float beta1, float beta2, float eps, int32_t t, void* stream)
+{
+    if (n <= 0) return fail(FDK_E_INVALID, "n must be positive");
+    if (!p || !g || !m || !v) return fail(FDK_E_INVALID, "p/g/m/v pointer is NULL");
+    if (t < 1) return fail(FDK_E_INVALID, "step t starts at 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) ||
+        !std::isfinite(lr))
+        return fail(FDK_E_INVALID, "Adam needs 0 <= beta < 1, eps > 0, finite lr");
+    return launch_adam(n, p, g, m, v, lr, beta1, beta2, eps, t, stream);
+}

@@ -68,9 +68,21 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const FilterArgs
     }
 }
 
-}  // namespace
+// Step 1 alone (the input of the learned row filter): q = raw * cosine weight.
+__global__ __launch_bounds__(kFilterThreads) void cosine_kernel(const FilterArgs A, int64_t n)
+{
+    for (int64_t q = (int64_t)blockIdx.x * kFilterThreads + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * kFilterThreads) {
+        const int64_t row = q / A.nw;
+        const int c = (int)(q - row * A.nw);
+        const int r = (int)(row % A.nh);
+        const float vmm = ((float)r - A.cv) * A.dv;
+        const float umm = ((float)c - A.cu) * A.du;
+        A.out[q] = A.raw[q] * (A.sdd * rsqrtf(fmaf(umm, umm, A.sdd2 + vmm * vmm)));
+    }
+}
 
-fdk_status launch_filter(const FilterLaunch& a, void* stream)
+FilterArgs filter_args(const FilterLaunch& a)
 {
     const double tau = a.du * a.sod / a.sdd;
     const double wang = a.arc / (2.0 * (double)a.np_total);
@@ -88,6 +100,25 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
     A.sdd2 = (float)(a.sdd * a.sdd);
     A.h0 = (float)(1.0 / (4.0 * tau * tau) * tau * wang);
     A.hscale = (float)(-1.0 / (pi * pi * tau * tau) * tau * wang);
+    return A;
+}
+
+}  // namespace
+
+fdk_status launch_cosine_weight(const FilterLaunch& a, void* stream)
+{
+    const FilterArgs A = filter_args(a);
+    const int64_t n = (int64_t)a.np * a.nh * a.nw;
+    int64_t blocks = (n + kFilterThreads - 1) / kFilterThreads;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(cosine_kernel, dim3((unsigned)blocks), dim3(kFilterThreads), 0,
+                       (hipStream_t)stream, A, n);
+    return check_launch("cosine-weight kernel");
+}
+
+fdk_status launch_filter(const FilterLaunch& a, void* stream)
+{
+    const FilterArgs A = filter_args(a);
     const int64_t rows = (int64_t)a.np * a.nh;
     if (rows >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "too many detector rows");
     const size_t lds = (size_t)(a.nw + (a.nw + 1) / 2 + 1) * sizeof(float);

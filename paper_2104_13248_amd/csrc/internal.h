@@ -103,6 +103,24 @@ struct FilterLaunch {
     int32_t np_total;
 };
 fdk_status launch_filter(const FilterLaunch& a, void* stream);
+// Cosine weight only (step 1 of the filter); uses raw, out, np, nh, nw, du,
+// dv, sdd, u_off, v_off of `a`.
+fdk_status launch_cosine_weight(const FilterLaunch& a, void* stream);
+
+// Learned row filter (float32, [rows][channels][len], weights [cout][cin][9]).
+fdk_status launch_conv1d_forward(int cin, int cout, int rows, int len, const float* in,
+                                 const float* w, const float* bias, const float* mask,
+                                 const float* add, float alpha, int relu, float* out,
+                                 void* stream);
+fdk_status launch_conv1d_backward_data(int cin, int cout, int rows, int len, const float* gout,
+                                       const float* w, const float* mask, float* gin,
+                                       void* stream);
+fdk_status launch_conv1d_backward_weight(int cin, int cout, int rows, int len, const float* in,
+                                         const float* gout, float* gw, float* gb, void* stream);
+fdk_status launch_sqerr(int64_t n, const float* a, const float* b, float* grad, float scale,
+                        float* loss, void* stream);
+fdk_status launch_adam(int n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int step, void* stream);
 
 fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16_t* out,
                                float* scale, void* stream);

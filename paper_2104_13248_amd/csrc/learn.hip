@@ -1,0 +1,385 @@
+// Kernels of the learned row filter (an extension of the FDK filtering step,
+// which the paper takes as given, Sections 2.1.2 and 3.1.1): 1-D convolutions
+// along detector rows -- forward, backward with respect to the input, backward
+// with respect to the weights -- with a fused ReLU / ReLU-gradient mask and a
+// fused residual addend, the squared-error loss of a reconstruction and an
+// Adam step.
+//
+// Tensors are float32 [rows][channels][len] (one detector row per `rows`
+// index, its channels contiguous along len).  Weights are [cout][cin][k],
+// bias [cout].  Convolution is cross-correlation with zero padding of k/2 on
+// both sides ("same" length):
+//   out[r][o][x] = bias[o] + sum_i sum_t w[o][i][t] in[r][i][x + t - k/2].
+// Instantiated for the filter network's shapes: cin, cout in {1, 32}, k = 9.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace fdk {
+namespace {
+
+constexpr int kK = 9;            // taps
+constexpr int kHalo = kK / 2;
+constexpr int kCT = 256;         // threads per block
+
+// Launch shape of the layer kernel for COUT output channels: G wave-uniform
+// channel groups of COUT / G channels, PPT consecutive positions per thread,
+// SEG positions per block, NT threads.
+template <int COUT>
+struct ConvShape {
+    static constexpr int G = COUT >= 4 ? 4 : 1;
+    static constexpr int PPT = COUT >= 4 ? 4 : 2;
+    static constexpr int NT = COUT >= 4 ? 256 : 128;
+    static constexpr int SEG = NT / G * PPT;
+};
+
+template <int N>
+__device__ __forceinline__ void lds_read(const float* p, float (&v)[N])
+{
+    // N consecutive floats from an address aligned to 4 (N % 4 == 0) or 2 floats
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < N / 4; ++q) {
+            const float4 t = reinterpret_cast<const float4*>(p)[q];
+            v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < N / 2; ++q) {
+            const float2 t = reinterpret_cast<const float2*>(p)[q];
+            v[2 * q] = t.x; v[2 * q + 1] = t.y;
+        }
+    }
+}
+
+// Forward convolution, or (TRANS) the backward-data convolution: the
+// transpose of a layer with weights w[OUT][IN][k] maps gradients of its
+// OUT-channel output back to its IN channels, and is itself a convolution with
+// channels swapped and taps mirrored:
+//   gin[r][i][x] = sum_o sum_t w[o][i][k-1-t] gout[r][o][x + t - k/2].
+// Here CIN/COUT are the channel counts of the convolution computed (for TRANS:
+// CIN = layer OUT, COUT = layer IN).
+//
+// Epilogue: y = bias + conv; ReLU if relu; y = 0 where mask <= 0 (mask is the
+// same shape as out); y = alpha y; y += add[...] (same shape as out).
+//
+// Block: one row segment of SEG positions, all output channels.  Each wave
+// owns one group of COUT / G channels, so every weight is a wave-uniform
+// (scalar) operand; each lane owns PPT consecutive positions and reads the
+// PPT + 8 input samples they need with aligned vector LDS loads, so every
+// sample read feeds 9 * PPT / (PPT + 8) multiply-adds per channel.
+template <int CIN, int COUT, bool TRANS>
+__global__ __launch_bounds__(ConvShape<COUT>::NT) void conv_kernel(
+    const float* __restrict__ in, const float* __restrict__ w, const float* __restrict__ bias,
+    const float* __restrict__ mask, const float* add, float alpha, int relu, float* out, int len,
+    int nseg)
+{
+    using S = ConvShape<COUT>;
+    constexpr int CPT = COUT / S::G;          // output channels per thread
+    constexpr int TP = S::SEG + 2 * kHalo;    // staged samples per channel (multiple of 4)
+    constexpr int NV = S::PPT + kK - 1;       // samples one lane reads per channel
+    static_assert(COUT % S::G == 0 && TP % 4 == 0, "shape");
+    __shared__ __attribute__((aligned(16))) float tile[CIN][TP];
+    const int r = blockIdx.x / nseg;
+    const int x0 = (blockIdx.x - r * nseg) * S::SEG;
+    const float* src = in + (size_t)r * CIN * len;
+    for (int q = threadIdx.x; q < CIN * TP; q += S::NT) {
+        const int ci = q / TP, xx = q - ci * TP;
+        const int x = x0 + xx - kHalo;
+        tile[ci][xx] = (x >= 0 && x < len) ? src[(size_t)ci * len + x] : 0.f;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int c0 = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) % S::G * CPT;
+    const int xl = (((int)threadIdx.x >> 6) / S::G * 64 + lane) * S::PPT;
+    float acc[CPT][S::PPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const float b0 = bias ? bias[c0 + c] : 0.f;
+#pragma unroll
+        for (int p = 0; p < S::PPT; ++p) acc[c][p] = b0;
+    }
+    constexpr int UNR = CPT >= 8 ? 1 : 4;     // bounds the weights held in SGPRs
+#pragma unroll UNR
+    for (int ci = 0; ci < CIN; ++ci) {
+        float v[NV];
+        lds_read(&tile[ci][xl], v);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+#pragma unroll
+            for (int t = 0; t < kK; ++t) {
+                const float wt = TRANS ? w[((size_t)ci * COUT + c0 + c) * kK + (kK - 1 - t)]
+                                       : w[((size_t)(c0 + c) * CIN + ci) * kK + t];
+#pragma unroll
+                for (int p = 0; p < S::PPT; ++p) acc[c][p] = fmaf(wt, v[p + t], acc[c][p]);
+            }
+        }
+    }
+    const size_t o = (size_t)r * COUT * len + x0 + xl;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const size_t oc = o + (size_t)(c0 + c) * len;
+#pragma unroll
+        for (int p = 0; p < S::PPT; ++p) {
+            if (x0 + xl + p < len) {
+                float y = acc[c][p];
+                if (relu) y = fmaxf(y, 0.f);
+                if (mask && !(mask[oc + p] > 0.f)) y = 0.f;
+                y *= alpha;
+                if (add) y += add[oc + p];
+                out[oc + p] = y;
+            }
+        }
+    }
+}
+
+// grad_w[o][i][t] += sum_{r,x} gout[r][o][x] in[r][i][x + t - k/2]
+// grad_b[o]       += sum_{r,x} gout[r][o][x]
+// Thread (pair, s) owns NPT (o, i) pairs with their k taps and the s-th of
+// SPLIT sub-segments of each staged segment (SPLIT > 1 only when there are
+// fewer pairs than threads).  A block walks a run of rows in segments of SEG
+// positions staged in LDS (input rows padded to an odd pitch so that the 32
+// channels a wave reads fall in distinct banks), reduces the SPLIT partial
+// sums in LDS and adds the block's sums with one float atomic per weight.
+template <int CIN, int COUT>
+struct WgradShape {
+    static constexpr int PAIRS = CIN * COUT;
+    static constexpr int NPT = (PAIRS + kCT - 1) / kCT;
+    static constexpr int SPLIT = PAIRS >= kCT ? 1 : (kCT / PAIRS > 8 ? 8 : kCT / PAIRS);
+};
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(kCT) void conv_wgrad_kernel(const float* __restrict__ in,
+                                                         const float* __restrict__ go,
+                                                         float* __restrict__ gw,
+                                                         float* __restrict__ gb, int rows,
+                                                         int len, int rows_per_block)
+{
+    using S = WgradShape<CIN, COUT>;
+    constexpr int SEG = 64;
+    constexpr int SUB = SEG / S::SPLIT;       // positions per sub-segment
+    constexpr int TP = SEG + 2 * kHalo + 1;   // odd pitch
+    constexpr int NRED = S::SPLIT > 1 ? S::SPLIT * S::PAIRS * (kK + 1) : 1;
+    __shared__ float tin[CIN][TP];
+    __shared__ float tgo[COUT][SEG];
+    __shared__ float red[NRED];
+    const int split = (int)threadIdx.x / (S::SPLIT > 1 ? S::PAIRS : kCT);
+    const bool active = split < S::SPLIT;
+    float acc[S::NPT][kK];
+    float accb[S::NPT];
+    int co_[S::NPT], ci_[S::NPT];
+#pragma unroll
+    for (int q = 0; q < S::NPT; ++q) {
+        const int pid = S::SPLIT > 1 ? (int)threadIdx.x % S::PAIRS : (int)threadIdx.x + kCT * q;
+        co_[q] = pid < S::PAIRS ? pid / CIN : 0;
+        ci_[q] = pid < S::PAIRS ? pid % CIN : 0;
+        accb[q] = 0.f;
+#pragma unroll
+        for (int t = 0; t < kK; ++t) acc[q][t] = 0.f;
+    }
+    const int r0 = blockIdx.x * rows_per_block;
+    const int r1 = min(rows, r0 + rows_per_block);
+    for (int r = r0; r < r1; ++r) {
+        const float* src = in + (size_t)r * CIN * len;
+        const float* g = go + (size_t)r * COUT * len;
+        for (int x0 = 0; x0 < len; x0 += SEG) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < CIN * (SEG + 2 * kHalo); q += kCT) {
+                const int ci = q / (SEG + 2 * kHalo), xx = q - ci * (SEG + 2 * kHalo);
+                const int x = x0 + xx - kHalo;
+                tin[ci][xx] = (x >= 0 && x < len) ? src[(size_t)ci * len + x] : 0.f;
+            }
+            for (int q = threadIdx.x; q < COUT * SEG; q += kCT) {
+                const int co = q / SEG, xx = q - co * SEG;
+                const int x = x0 + xx;
+                tgo[co][xx] = x < len ? g[(size_t)co * len + x] : 0.f;
+            }
+            __syncthreads();
+            if (!active) continue;
+#pragma unroll
+            for (int q = 0; q < S::NPT; ++q) {
+                const float* ti = &tin[ci_[q]][split * SUB];
+                const float* tg = &tgo[co_[q]][split * SUB];
+                float win[kK];
+#pragma unroll
+                for (int t = 0; t < kK - 1; ++t) win[t + 1] = ti[t];
+#pragma unroll
+                for (int xx = 0; xx < SUB; ++xx) {
+#pragma unroll
+                    for (int t = 0; t < kK - 1; ++t) win[t] = win[t + 1];
+                    win[kK - 1] = ti[xx + kK - 1];
+                    const float gv = tg[xx];
+                    accb[q] += gv;
+#pragma unroll
+                    for (int t = 0; t < kK; ++t) acc[q][t] = fmaf(gv, win[t], acc[q][t]);
+                }
+            }
+        }
+    }
+    if constexpr (S::SPLIT > 1) {
+        if (active) {
+            const int pid = (int)threadIdx.x % S::PAIRS;
+            float* dst = red + ((size_t)split * S::PAIRS + pid) * (kK + 1);
+#pragma unroll
+            for (int t = 0; t < kK; ++t) dst[t] = acc[0][t];
+            dst[kK] = accb[0];
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < S::PAIRS * (kK + 1); q += kCT) {
+            float sum = 0.f;
+#pragma unroll
+            for (int s2 = 0; s2 < S::SPLIT; ++s2) sum += red[(size_t)s2 * S::PAIRS * (kK + 1) + q];
+            const int pid = q / (kK + 1), t = q - pid * (kK + 1);
+            if (t < kK) {
+                unsafeAtomicAdd(gw + (size_t)pid * kK + t, sum);
+            } else if (gb && pid % CIN == 0) {
+                unsafeAtomicAdd(gb + pid / CIN, sum);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < S::NPT; ++q) {
+            const int pid = (int)threadIdx.x + kCT * q;
+            if (pid < S::PAIRS) {
+#pragma unroll
+                for (int t = 0; t < kK; ++t) unsafeAtomicAdd(gw + (size_t)pid * kK + t, acc[q][t]);
+                if (gb && ci_[q] == 0) unsafeAtomicAdd(gb + co_[q], accb[q]);
+            }
+        }
+    }
+}
+
+// loss[0] += sum (a - b)^2 ;  grad = scale (a - b)  (scale = 2/n: gradient of the mean)
+__global__ __launch_bounds__(256) void sqerr_kernel(const float* __restrict__ a,
+                                                    const float* __restrict__ b,
+                                                    float* __restrict__ grad, float scale,
+                                                    int64_t n, float* __restrict__ loss)
+{
+    __shared__ float part[4];
+    float s = 0.f;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const float d = a[q] - b[q];
+        s = fmaf(d, d, s);
+        if (grad) grad[q] = scale * d;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) unsafeAtomicAdd(loss, (part[0] + part[1]) + (part[2] + part[3]));
+}
+
+// Adam (Kingma and Ba, ICLR 2015, Algorithm 1):
+//   m = b1 m + (1 - b1) g;  v = b2 v + (1 - b2) g^2;
+//   p -= lr (m / c1) / (sqrt(v / c2) + eps),  c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, int n, float lr,
+                            float b1, float b2, float eps, float c1, float c2)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const float gq = g[q];
+    const float mq = fmaf(b1, m[q], (1.f - b1) * gq);
+    const float vq = fmaf(b2, v[q], (1.f - b2) * gq * gq);
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+template <int CIN, int COUT, bool TRANS>
+fdk_status conv(int rows, int len, const float* in, const float* w, const float* b,
+                const float* mask, const float* add, float alpha, int relu, float* out,
+                hipStream_t st)
+{
+    using S = ConvShape<COUT>;
+    const int nseg = (len + S::SEG - 1) / S::SEG;
+    if ((int64_t)nseg * rows >= (1ll << 31))
+        return fail(FDK_E_UNSUPPORTED, "conv1d tensor too large for one launch");
+    hipLaunchKernelGGL((conv_kernel<CIN, COUT, TRANS>), dim3((unsigned)(nseg * rows)), dim3(S::NT),
+                       0, st, in, w, b, mask, add, alpha, relu, out, len, nseg);
+    return check_launch(TRANS ? "conv1d backward-data kernel" : "conv1d forward kernel");
+}
+
+template <int CIN, int COUT>
+fdk_status wgrad(int rows, int len, const float* in, const float* go, float* gw, float* gb,
+                 hipStream_t st)
+{
+    // about 1024 blocks: enough to fill 256 CUs, few atomics per weight
+    int rpb = (rows + 1023) / 1024;
+    if (rpb < 1) rpb = 1;
+    const int blocks = (rows + rpb - 1) / rpb;
+    hipLaunchKernelGGL((conv_wgrad_kernel<CIN, COUT>), dim3((unsigned)blocks), dim3(kCT), 0, st,
+                       in, go, gw, gb, rows, len, rpb);
+    return check_launch("conv1d weight-gradient kernel");
+}
+
+bool supported(int cin, int cout)
+{
+    return (cin == 1 || cin == 32) && (cout == 1 || cout == 32);
+}
+
+}  // namespace
+
+fdk_status launch_conv1d_forward(int cin, int cout, int rows, int len, const float* in,
+                                 const float* w, const float* bias, const float* mask,
+                                 const float* add, float alpha, int relu, float* out,
+                                 void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (!supported(cin, cout))
+        return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
+    if (cin == 1 && cout == 32) return conv<1, 32, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    if (cin == 32 && cout == 32) return conv<32, 32, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    if (cin == 32 && cout == 1) return conv<32, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    return conv<1, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+}
+
+fdk_status launch_conv1d_backward_data(int cin, int cout, int rows, int len, const float* gout,
+                                       const float* w, const float* mask, float* gin, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (!supported(cin, cout))
+        return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
+    // the transposed convolution reads `cout` channels and writes `cin`
+    if (cin == 1 && cout == 32) return conv<32, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    if (cin == 32 && cout == 32) return conv<32, 32, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    if (cin == 32 && cout == 1) return conv<1, 32, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    return conv<1, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+}
+
+fdk_status launch_conv1d_backward_weight(int cin, int cout, int rows, int len, const float* in,
+                                         const float* gout, float* gw, float* gb, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    if (!supported(cin, cout))
+        return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
+    if (cin == 1 && cout == 32) return wgrad<1, 32>(rows, len, in, gout, gw, gb, st);
+    if (cin == 32 && cout == 32) return wgrad<32, 32>(rows, len, in, gout, gw, gb, st);
+    if (cin == 32 && cout == 1) return wgrad<32, 1>(rows, len, in, gout, gw, gb, st);
+    return wgrad<1, 1>(rows, len, in, gout, gw, gb, st);
+}
+
+fdk_status launch_sqerr(int64_t n, const float* a, const float* b, float* grad, float scale,
+                        float* loss, void* stream)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(sqerr_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a,
+                       b, grad, scale, n, loss);
+    return check_launch("squared-error kernel");
+}
+
+fdk_status launch_adam(int n, float* p, const float* g, float* m, float* v, float lr, float b1,
+                       float b2, float eps, int step, void* stream)
+{
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return check_launch("adam kernel");
+}
+
+}  // namespace fdk

@@ -4,6 +4,7 @@ header declares, and rejects bad arguments on the host before any HIP call.
 Device pointers here are fake non-NULL addresses: every case is rejected by
 host-side validation before the library would touch them."""
 import ctypes
+import glob
 import math
 import os
 import re
@@ -24,9 +25,11 @@ OK, E_INVALID, E_GEOMETRY, E_UNSUPPORTED = 0, -1, -2, -3
 
 
 def header_functions():
-    text = open(os.path.join(ROOT, "include", "fdk.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fdk_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(fdk_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_match_header():
@@ -236,3 +239,33 @@ def test_plan_covers_every_footprint(name):
     assert full <= plan["rows_full"]
     assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4
     assert plan["fp_lds_bytes"] >= plan["rows_full"] * plan["lds_pitch"] * 4
+
+
+def test_learned_filter_entry_points_validate():
+    lib = _lib.lib
+    # unsupported channel counts, bad sizes, NULL pointers: rejected on the host
+    assert lib.fdk_conv1d_forward(16, 32, 4, 8, FAKE, FAKE, None, None, None, 1.0, 0, FAKE,
+                                  None) == E_UNSUPPORTED
+    assert lib.fdk_conv1d_forward(1, 32, 0, 8, FAKE, FAKE, None, None, None, 1.0, 0, FAKE,
+                                  None) == E_INVALID
+    assert lib.fdk_conv1d_forward(1, 32, 4, 8, None, FAKE, None, None, None, 1.0, 0, FAKE,
+                                  None) == E_INVALID
+    assert lib.fdk_conv1d_forward(1, 32, 4, 8, FAKE, FAKE, None, None, None, math.inf, 0,
+                                  ctypes.c_void_p(0x20000), None) == E_INVALID
+    assert lib.fdk_conv1d_backward_data(32, 5, 4, 8, FAKE, FAKE, None, FAKE, None) == E_UNSUPPORTED
+    assert lib.fdk_conv1d_backward_data(32, 32, 4, 8, FAKE, FAKE, None, FAKE, None) == E_INVALID
+    assert lib.fdk_conv1d_backward_weight(32, 32, 4, -1, FAKE, FAKE, FAKE, None, None) == E_INVALID
+    assert lib.fdk_conv1d_backward_weight(32, 32, 4, 8, FAKE, FAKE, None, None, None) == E_INVALID
+    assert lib.fdk_sqerr(0, FAKE, FAKE, None, 1.0, FAKE, None) == E_INVALID
+    assert lib.fdk_sqerr(10, FAKE, FAKE, None, 1.0, None, None) == E_INVALID
+    assert lib.fdk_adam(10, FAKE, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E_INVALID
+    assert lib.fdk_adam(10, FAKE, FAKE, FAKE, FAKE, 1e-3, 1.0, 0.999, 1e-8, 1, None) == E_INVALID
+    assert lib.fdk_adam(10, FAKE, FAKE, FAKE, FAKE, 1e-3, 0.9, 0.999, 0.0, 1, None) == E_INVALID
+    sg = _lib.stack_struct(2, 3, 4)
+    assert lib.fdk_cosine_weight(ctypes.byref(sg), FAKE, None, 1.0, 1.0, 100.0, 0.0, 0.0,
+                                 None) == E_INVALID
+    assert lib.fdk_cosine_weight(ctypes.byref(sg), FAKE, FAKE, 1.0, -1.0, 100.0, 0.0, 0.0,
+                                 None) == E_INVALID
+    bad = _lib.stack_struct(2, 3, 4, _lib.FDK_F16)
+    assert lib.fdk_cosine_weight(ctypes.byref(bad), FAKE, FAKE, 1.0, 1.0, 100.0, 0.0, 0.0,
+                                 None) != OK

@@ -50,7 +50,9 @@ extern "C" fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, con
     out[6] = plan.blocks;
     out[7] = kThreads;
     out[8] = plan.rows_full;
-    out[9] = plan.fp_lds_bytes;
+    FpPlan fpp;
+    s = make_fp_plan(*vg, *sg, fpp);
+    out[9] = s == FDK_OK ? fpp.lds_bytes : 0;
     return FDK_OK;
 }
 
@@ -123,33 +125,44 @@ extern "C" fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
     if (s != FDK_OK) return s;
     if (!vol) return fail(FDK_E_INVALID, "volume pointer is NULL");
     if (!proj) return fail(FDK_E_INVALID, "projection pointer is NULL");
-    BpPlan plan;
-    s = make_bp_plan(*vg, *sg, M, plan);
+    FpPlan plan;
+    s = make_fp_plan(*vg, *sg, plan);
     if (s != FDK_OK) return s;
+    std::vector<int32_t> swap;
+    fp_swap_flags(*vg, M, swap);
+    bool any_swap = false;
+    for (int32_t f : swap) any_swap = any_swap || f;
     const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
+    const size_t vbytes = (size_t)vg->nx * vg->ny * vg->nz * sizeof(float);
     void* d_world = nullptr;
     void* d_index = nullptr;
+    void* d_swap = nullptr;
+    void* d_volT = nullptr;
     s = upload_async(mats, mbytes, stream, &d_world);
-    if (s != FDK_OK) return s;
-    s = device_alloc_async(mbytes, stream, &d_index);
-    if (s != FDK_OK) {
-        device_free_async(d_world, stream);
-        return s;
+    if (s == FDK_OK) s = upload_async(swap.data(), swap.size() * sizeof(int32_t), stream, &d_swap);
+    if (s == FDK_OK) s = device_alloc_async(mbytes, stream, &d_index);
+    if (s == FDK_OK && any_swap) s = device_alloc_async(vbytes, stream, &d_volT);
+    if (s == FDK_OK) {
+        FpLaunch a;
+        a.vol = vol;
+        a.volT = (float*)d_volT;
+        a.swap = (const int*)d_swap;
+        a.proj = proj;
+        a.mats_world = (const double*)d_world;
+        a.mats_index = (double*)d_index;
+        a.nx = vg->nx; a.ny = vg->ny; a.nz = vg->nz;
+        a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
+        a.dx = vg->dx; a.dy = vg->dy; a.dz = vg->dz;
+        fill_grid(*vg, a.ox, a.oy, a.oz);
+        s = launch_forwardproject(a, plan, stream);
     }
-    FpLaunch a;
-    a.vol = vol;
-    a.proj = proj;
-    a.mats_world = (const double*)d_world;
-    a.mats_index = (double*)d_index;
-    a.nx = vg->nx; a.ny = vg->ny; a.nz = vg->nz;
-    a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
-    a.dx = vg->dx; a.dy = vg->dy; a.dz = vg->dz;
-    fill_grid(*vg, a.ox, a.oy, a.oz);
-    s = launch_forwardproject(a, plan, stream);
-    fdk_status s2 = device_free_async(d_index, stream);
-    fdk_status s3 = device_free_async(d_world, stream);
-    if (s != FDK_OK) return s;
-    return s2 != FDK_OK ? s2 : s3;
+    fdk_status s2 = FDK_OK;
+    for (void* d : {d_volT, d_index, d_swap, d_world})
+        if (d) {
+            fdk_status e = device_free_async(d, stream);
+            if (s2 == FDK_OK) s2 = e;
+        }
+    return s != FDK_OK ? s : s2;
 }
 
 extern "C" fdk_status fdk_filter(const fdk_stack* sg, const float* raw, float* out, double du,

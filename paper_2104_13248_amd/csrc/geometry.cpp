@@ -262,7 +262,6 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
         if (!pitch) continue;
         const int rows = std::max(e.rows_half, std::min(e.rows_p95, e.rows_full));
         const int64_t bytes = (int64_t)rows * pitch * 4 + table_bytes;
-        const int64_t fp_bytes = (int64_t)e.rows_full * pitch * 4 + table_bytes;
         if (bytes > 150 * 1024) continue;
         if (!found || (best_bytes > lds_budget && bytes < best_bytes)) {
             best.kz = kz;
@@ -271,7 +270,6 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
             best.rows_full = e.rows_full;
             best.cols = e.cols;
             best.lds_bytes = bytes;
-            best.fp_lds_bytes = fp_bytes;
             best_bytes = bytes;
             found = true;
         }
@@ -291,6 +289,20 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
     g_plans.emplace_front(h, best);
     if (g_plans.size() > 32) g_plans.pop_back();
     return FDK_OK;
+}
+
+void fp_swap_flags(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
+                   std::vector<int32_t>& swap)
+{
+    const double ic = 0.5 * (vg.nx - 1), jc = 0.5 * (vg.ny - 1);
+    swap.resize(M.size());
+    for (size_t s = 0; s < M.size(); ++s) {
+        const double* m = M[s].m;
+        const double w = m[8] * ic + m[9] * jc + m[11];
+        const double u = (m[0] * ic + m[1] * jc + m[3]) / w;
+        const double dui = (m[0] - u * m[8]) / w, duj = (m[1] - u * m[9]) / w;
+        swap[s] = std::fabs(duj) > std::fabs(dui) ? 1 : 0;
+    }
 }
 
 }  // namespace fdk

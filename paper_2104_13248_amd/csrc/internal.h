@@ -46,7 +46,6 @@ struct BpPlan {
     int cols = 0;        // maximum footprint width
     int ntx = 0, nty = 0, ntiles_pad = 0, nchunks = 0;
     int64_t lds_bytes = 0;      // back-projector LDS per block
-    int64_t fp_lds_bytes = 0;   // forward projector LDS per block (no splitting)
     int64_t blocks = 0;
 };
 
@@ -85,15 +84,33 @@ struct BpLaunch {
 };
 fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* stream);
 
+// Forward projector: a block per (band of rb detector rows, chunk of columns, view).
+struct FpPlan {
+    int rb = 0;          // detector rows per band
+    int pitch = 0;       // LDS window pitch (columns per chunk + 2)
+    int nbands = 0;
+    int ncb = 0;         // column chunks
+    int64_t lds_bytes = 0;
+    int64_t blocks = 0;
+};
+fdk_status make_fp_plan(const fdk_volume& vg, const fdk_stack& sg, FpPlan& plan);
+int64_t fp_lds_bytes(int rb, int nw);
+
+// Views whose lanes should run along y: |du/dj| > |du/di| at the volume centre.
+void fp_swap_flags(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
+                   std::vector<int32_t>& swap);
+
 struct FpLaunch {
     const float* vol;
+    float* volT;             // scratch [nz][nx][ny] when any view swaps, else nullptr
+    const int* swap;         // device [np]
     float* proj;
     const double* mats_world;
     double* mats_index;
     int32_t nx, ny, nz, np, nh, nw;
     double dx, dy, dz, ox, oy, oz;
 };
-fdk_status launch_forwardproject(const FpLaunch& a, const BpPlan& plan, void* stream);
+fdk_status launch_forwardproject(const FpLaunch& a, const FpPlan& plan, void* stream);
 
 struct FilterLaunch {
     const float* raw;

@@ -238,7 +238,11 @@ def test_plan_covers_every_footprint(name):
     assert half <= plan["lds_rows"]
     assert full <= plan["rows_full"]
     assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4
-    assert plan["fp_lds_bytes"] >= plan["rows_full"] * plan["lds_pitch"] * 4
+    # forward projector: a window of (band rows + 2) x (nw + 2) floats, within the default budget
+    fp = plan["fp_lds_bytes"]
+    pitch = min(cfg["nw"], 256) + 2
+    assert fp % (4 * pitch) == 0 and fp // (4 * pitch) >= 3
+    assert fp <= 16 * 1024
 
 
 def test_learned_filter_entry_points_validate():

@@ -56,6 +56,56 @@ def test_forward_projection_parity(case):
     assert e <= TOL32
 
 
+@pytest.fixture
+def small_fp_budget(monkeypatch):
+    """Forward-projector LDS budget of a few rows, so that every detector is
+    split into many row bands (band boundaries inside every footprint)."""
+    monkeypatch.setenv("FDK_FP_LDS_BUDGET", "2600")
+
+
+@pytest.mark.parametrize("case", range(len(FP_CASES)))
+def test_forward_projection_many_bands(case, small_fp_budget):
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
+    scan = dict(wl.CONFIGS[name]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    rb = fdk.bp_plan(shape, (1.0, 1.0, 1.0), npv, nh, nw, mats, centre)["fp_lds_bytes"] \
+        // (4 * (min(nw, 256) + 2)) - 2
+    assert rb < nh // 3
+    x = wl.gaussian(540 + case, shape)
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    e = rel(got, ref)
+    log("fp many bands case", case, "rb", rb, "rel-L2", e)
+    assert e <= TOL32
+
+
+@pytest.mark.parametrize("theta0", [math.pi / 2 - 0.3, -0.3, 0.25 * math.pi - 0.3])
+def test_forward_projection_view_orientations(theta0):
+    """Short arcs whose views all run lanes along x (no transposed copy), all
+    along y (transposed copy only), and a mix across the 45-degree switch."""
+    cfg = wl.CONFIGS["c1"]
+    scan = dict(cfg["scan"], arc=0.6, theta0=theta0)
+    shape, npv, nh, nw = (40, 36, 44), 20, 64, 96
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    x = wl.gaussian(560, shape)
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0))
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0))
+    assert rel(got, ref) <= TOL32
+
+
+def test_forward_projection_c5_geometry():
+    """Magnification-2 sampling of the learned-filter workload (0.25 mm voxels,
+    0.25 mm pixels) on a 48^3 crop, 30 views, full 512^2 detector."""
+    cfg = wl.CONFIGS["c5"]
+    mats = og.scan_matrices(cfg["scan"], 30, cfg["nh"], cfg["nw"])
+    x = wl.gaussian(570, (48, 48, 48))
+    centre = (1.5, -2.0, 0.75)
+    got = gpu_fp(x, mats, cfg["nh"], cfg["nw"], cfg["voxel"], centre)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, cfg["nh"], cfg["nw"], cfg["voxel"],
+                                centre)
+    assert rel(got, ref) <= TOL32
+
+
 def test_forward_projection_accumulates():
     name, shape, (npv, nh, nw), over, centre = FP_CASES[1]
     mats = og.scan_matrices(dict(wl.CONFIGS[name]["scan"], **over), npv, nh, nw)

@@ -18,8 +18,10 @@ the host's cores on a bounded sub-block of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +36,40 @@ OPS_PER_UPDATE = 10
 # FP32 VALU lane-operations.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# Calibration copy for the HBM byte counters: a plain device-to-device copy of
+# this many bytes, run once when --calibrate-copy is given.
+CALIBRATION_BYTES = 1 << 30
+# Measured HBM traffic of the back-projection kernel (FETCH_SIZE + WRITE_SIZE,
+# scaled by the calibration copy) and the hash of the sources it was taken on.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_kernel_c2_512cube_1024views_traffic.md")
+KERNEL_SOURCES = ("bp.hip", "footprint.h", "internal.h", "geometry.cpp")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_13248_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the FP16 back-projection from the committed
+    counter summary, or None if it is missing, for another workload, or taken
+    on other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", text, flags=re.M))
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if fields.get("workload") != workload:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -82,6 +118,8 @@ def main() -> int:
     ap.add_argument("--config", default="c2")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the back-projector has no multi-GPU path in this "
@@ -117,6 +155,15 @@ def main() -> int:
     del raw
     torch.cuda.synchronize()
     log("input ready: filtered stack %.2f GiB" % (filt.numel() * 4 / 2**30))
+
+    if args.calibrate_copy:
+        src = torch.ones(CALIBRATION_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: %d bytes" % CALIBRATION_BYTES)
 
     vol = torch.zeros(cfg["shape"], dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -165,6 +212,8 @@ def main() -> int:
     achieved = n_upd * OPS_PER_UPDATE / k_s / 1e12
     vol_bytes = nx * ny * nz * 4
     hbm_alg = 2 * vol_bytes + npv * nh * nw * 2 + npv * 4           # volume RMW + f16 stack
+    workload = "fdk_backprojection_%dx%dx%d_%dviews_%dx%d" % (nx, ny, nz, npv, nh, nw)
+    traffic = measured_traffic(workload)
     out = {
         "metric": "GUPS (giga voxel-updates/s) FDK backproject, FP16-store vs FP32 at rel-L2<=1e-3",
         "value": f16["gups"],
@@ -179,7 +228,7 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic: GPU analytic line integrals of a seeded 40-ellipsoid phantom, "
                 "FDK ramp-filtered; FP16 storage with per-view scale",
-        "config": {"workload": "fdk_backprojection_%dx%dx%d_%dviews_%dx%d" % (nx, ny, nz, npv, nh, nw),
+        "config": {"workload": workload,
                    "volume": [nz, ny, nx], "voxel_mm": list(cfg["voxel"]), "views": npv,
                    "detector": [nh, nw], "pixel_mm": [scan["du"], scan["dv"]],
                    "sod_mm": scan["sod"], "sdd_mm": scan["sdd"], "storage": "f16",
@@ -189,9 +238,10 @@ def main() -> int:
                          "kernel_ms": f32["kernel_ms"]},
         "f16_over_f32": f16["gups"] / f32["gups"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "bp_kernel", "kernel_ms": f16["kernel_ms"],
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                     "traffic_unit": "bytes/launch", "kernel": "bp_kernel", "kernel_ms": f16["kernel_ms"],
                      "ops_per_update": OPS_PER_UPDATE,
+                     "hbm_algorithmic_bytes": hbm_alg,
                      "hbm_algorithmic_gbs": hbm_alg / k_s / 1e9,
                      "hbm_frac": hbm_alg / k_s / 1e9 / HBM_PEAK_GBS},
     }

@@ -114,8 +114,11 @@ fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k
  * around its (u, v) with the interpolation weights of Listing 2; taps outside
  * the detector are dropped.  vol: device float32 [nz][ny][nx]; proj: device
  * float32 [np][nh][nw] (sg->dtype must be FDK_F32, else FDK_E_UNSUPPORTED),
- * accumulated into.  Uses float atomics: the summation order, and so the last
- * bits, are not deterministic.  Same geometry requirement as above.
+ * accumulated into.  Each projection sample is summed by one thread in a
+ * fixed order (no atomics): the result is deterministic.  Views whose u
+ * changes faster along y than along x read a transposed copy of the volume,
+ * a stream-ordered device allocation of the volume's size made by the call.
+ * Same geometry requirement as above.
  */
 fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
                               const fdk_stack* sg, float* proj,

@@ -106,6 +106,15 @@ def test_forward_projection_c5_geometry():
     assert rel(got, ref) <= TOL32
 
 
+def test_forward_projection_is_deterministic():
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[1]
+    mats = og.scan_matrices(dict(wl.CONFIGS[name]["scan"], **over), npv, nh, nw)
+    x = wl.gaussian(580, shape)
+    a = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    b = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    assert np.array_equal(a, b)
+
+
 def test_forward_projection_accumulates():
     name, shape, (npv, nh, nw), over, centre = FP_CASES[1]
     mats = og.scan_matrices(dict(wl.CONFIGS[name]["scan"], **over), npv, nh, nw)

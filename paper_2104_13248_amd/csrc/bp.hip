@@ -113,32 +113,58 @@ __device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rs
             }
         }
     } else {
-        // Groups of 63 pairs: lane 63 only supplies the right neighbour of
-        // lane 62.  Rows are loaded kRowBatch at a time so that the loads of
-        // a batch are in flight together before the first one is consumed.
-        constexpr int kRowBatch = 8;
-        for (int g = 0; g * 63 < C; ++g) {
-            const int cc = g * 63 + lane;
-            const int c = c0 + cc;
-            const unsigned voff = (unsigned)c < (unsigned)nw ? (unsigned)c * 2u : kOut;
-            const bool keep = lane < 63 && cc < C;
-            for (int rb0 = wave; rb0 < R; rb0 += kWaves * kRowBatch) {
-                unsigned lo[kRowBatch];
-#pragma unroll
-                for (int b = 0; b < kRowBatch; ++b) {
-                    const int rr = rb0 + kWaves * b;
-                    const int r = r0 + rr;
-                    lo[b] = 0u;
-                    if (rr < R && (unsigned)r < (unsigned)nh)
-                        lo[b] = __builtin_amdgcn_raw_buffer_load_b16(rs, voff, (unsigned)r * row_bytes, 0);
+        // Binary16 rows are staged as two half-rows of pair words by
+        // asynchronous dword loads straight into LDS: EV[m] holds pixels
+        // (ce+2m, ce+2m+1) (aligned loads) and OD[m] pixels (ce+2m+1, ce+2m+2)
+        // (2-byte aligned loads), ce = c0 rounded down to even.  The pair
+        // (p[c], p[c+1]) of column c is EV[(c-ce)/2] or OD[(c-ce-1)/2].  A word
+        // with one pixel outside the detector is rewritten afterwards from a
+        // 16-bit load of its valid pixel.
+        constexpr int HP = PITCH / 2;
+        const int ce = c0 & ~1;
+        int NE = (C + (c0 - ce) + 1) >> 1;
+        NE = NE < HP ? NE : HP;
+        for (int g = 0; g * 64 < NE; ++g) {
+            const int mm = g * 64 + lane;
+            const int pe = ce + 2 * mm, po = pe + 1;
+            const unsigned voe = (unsigned)pe < (unsigned)nw ? (unsigned)pe * 2u : kOut;
+            const unsigned voo = (unsigned)po < (unsigned)nw ? (unsigned)po * 2u : kOut;
+            const bool keep = mm < NE;
+            for (int rr = wave; rr < R; rr += kWaves) {
+                const int r = r0 + rr;
+                if ((unsigned)r < (unsigned)nh) {
+                    if (keep) {
+                        lds_void* de = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + g * 64);
+                        lds_void* dd = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + HP + g * 64);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, de, 4, voe, (unsigned)r * row_bytes, 0, 0);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dd, 4, voo, (unsigned)r * row_bytes, 0, 0);
+                    }
+                } else if (keep) {
+                    wtile[rr * PITCH + mm] = 0u;
+                    wtile[rr * PITCH + HP + mm] = 0u;
                 }
-#pragma unroll
-                for (int b = 0; b < kRowBatch; ++b) {
-                    const int rr = rb0 + kWaves * b;
-                    // DPP wave shift left by one lane: lane i receives (lane i+1) << 16
-                    const unsigned pair =
-                        __builtin_amdgcn_update_dpp(0u, lo[b] << 16, 0x130, 0xf, 0xf, false) | lo[b];
-                    if (keep && rr < R) wtile[rr * PITCH + cc] = pair;
+            }
+        }
+        // words straddling the detector edges (uniform test: the window
+        // reaches column -1 or column nw)
+        const int mleft = (-2 - ce) >> 1;                       // OD word (p[-1], p[0])
+        const int jr = nw - 1 - ce;                             // word starting at p[nw-1]
+        const int mright = jr >> 1, right_od = jr & 1;
+        const bool fix_left = ce <= -2 && mleft < NE;
+        const bool fix_right = jr >= 0 && mright < NE;
+        if (fix_left || fix_right) {
+            __builtin_amdgcn_s_waitcnt(0);                    // this wave's row loads landed
+            for (int rr = wave; rr < R; rr += kWaves) {
+                const int r = r0 + rr;
+                if ((unsigned)r >= (unsigned)nh) continue;
+                if (fix_left && lane == 0) {
+                    const unsigned p0 = __builtin_amdgcn_raw_buffer_load_b16(rs, 0u, (unsigned)r * row_bytes, 0);
+                    wtile[rr * PITCH + HP + mleft] = p0 << 16;
+                }
+                if (fix_right && lane == 1) {
+                    const unsigned pl = __builtin_amdgcn_raw_buffer_load_b16(
+                        rs, (unsigned)(nw - 1) * 2u, (unsigned)r * row_bytes, 0);
+                    wtile[rr * PITCH + (right_od ? HP : 0) + mright] = pl;
                 }
             }
         }
@@ -253,8 +279,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             const float dv = uniform(rv.m12) * F;
             const float W = F * F * uniform(rv.scale);
             const float fu = __builtin_amdgcn_fractf(u);
-            // LDS byte address of column floor(u) of tile row 0 (u >= 1 inside the tile)
-            const unsigned base = tile_base + 4u * (unsigned)(int)u;
+            // LDS byte address of the pair word of column floor(u) in tile row 0
+            // (u >= 1 inside the tile); binary16 rows hold even- and odd-offset
+            // pairs in two half-rows
+            unsigned base;
+            if (F16) {
+                const int j = (int)u + (uniform(rv.c0) & 1);
+                base = tile_base + 4u * (unsigned)((j >> 1) + ((j & 1) ? PITCH / 2 : 0));
+            } else {
+                base = tile_base + 4u * (unsigned)(int)u;
+            }
             // ---- hot loop: KZ updates of this column for this view, in two
             // halves; a footprint taller than the LDS tile is staged per half
 #pragma unroll

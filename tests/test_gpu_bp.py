@@ -182,6 +182,34 @@ def test_c2_full_size_sampled():
     assert e <= TOL32
 
 
+def test_c3_full_size_sampled_f16():
+    """1024^3 (0.5 mm) x 2048 views x 2048^2, binary16 storage with per-view
+    scales: the largest workload, in the launch the library makes for it.
+    The stored stack (seeded, generated on the GPU) is the input of both
+    sides; sampled voxels against the oracle evaluated one by one on the same
+    binary16 values, to the FP32 tolerance."""
+    cfg = wl.CONFIGS["c3"]
+    shape, npv, nh, nw = cfg["shape"], cfg["np"], cfg["nh"], cfg["nw"]
+    log("c3: generating", (npv, nh, nw))
+    h, s = wl.device_f16_stack(3001, (npv, nh, nw))
+    mats = og.scan_matrices(cfg["scan"], npv, nh, nw)
+    log("c3: plan", fdk.bp_plan(shape, cfg["voxel"], npv, nh, nw, mats, f16=True))
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, cfg["voxel"], scale=s)
+    torch.cuda.synchronize()
+    ijk = _sample_voxels(shape, 384, 11)
+    got = vol[ijk[:, 2], ijk[:, 1], ijk[:, 0]].cpu().numpy()
+    del vol
+    log("c3: copying the stack to the host")
+    h_np, s_np = h.cpu().numpy(), s.cpu().numpy()
+    del h
+    log("c3: oracle on", len(ijk), "voxels")
+    ref = oracle.backproject_points(h_np, mats, shape, cfg["voxel"], ijk, scale=s_np)
+    e = rel(got, ref)
+    log("c3 sampled rel-L2", e)
+    assert e <= TOL32
+
+
 # Strongly magnified cone geometries: some blocks' footprints are taller than
 # the LDS tile and are staged per half-chunk.
 SPLIT = [

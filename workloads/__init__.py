@@ -91,6 +91,25 @@ def gaussian(seed: int, shape, dtype=np.float32) -> np.ndarray:
     return rng.standard_normal(size=shape, dtype=np.float64 if dtype == np.float64 else np.float32)
 
 
+def device_f16_stack(seed: int, shape, device="cuda"):
+    """Seeded binary16 projection stack generated on the GPU (for sizes where
+    a host generator would be too slow): standard-normal values drawn by
+    torch's counter-based generator and rounded to binary16, plus one
+    power-of-two scale per view, 2^-(s mod 7).  Returned as (torch float16
+    [np, nh, nw], torch float32 [np]) on ``device``; both are inputs of the
+    stored (binary16 + scale) form, used unchanged by every consumer."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    h = torch.empty(tuple(shape), dtype=torch.float16, device=device)
+    for v0 in range(0, shape[0], 64):      # bounded float32 temporaries
+        n = min(64, shape[0] - v0)
+        h[v0:v0 + n] = torch.randn((n,) + tuple(shape[1:]), generator=g, device=device).half()
+    s = torch.tensor([2.0 ** -(v % 7) for v in range(shape[0])], dtype=torch.float32,
+                     device=device)
+    return h, s
+
+
 def shrink(cfg, shape=None, np_views=None, nh=None, nw=None):
     """A copy of ``cfg`` with smaller sizes (same physical pitch and distances)."""
     out = dict(cfg)

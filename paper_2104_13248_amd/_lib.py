@@ -1,5 +1,5 @@
-"""ctypes binding of libfdk.so (include/fdk.h, include/fdk_learn.h): argument
-marshalling only.
+"""ctypes binding of libfdk.so (include/fdk.h, fdk_learn.h, fdk_ablation.h):
+argument marshalling only.
 
 Every operation runs in the HIP kernels of the library; this module checks
 tensor placement, dtype and contiguity, passes raw device pointers and the
@@ -67,6 +67,8 @@ def _load():
         "fdk_conv1d_backward_weight": [I, I, I, I, P, P, P, P, P],
         "fdk_sqerr": [ctypes.c_int64, P, P, P, F, P, P],
         "fdk_adam": [I, P, P, P, P, F, F, F, F, I, P],
+        # include/fdk_ablation.h
+        "fdk_backproject_variant": [I, I, VP, P, SP, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -81,12 +83,13 @@ def _load():
 
 lib = _load()
 
-#: names declared in include/fdk.h and include/fdk_learn.h
+#: names declared in include/fdk.h, include/fdk_learn.h and include/fdk_ablation.h
 EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_forwardproject", "fdk_filter",
            "fdk_quantize_f16", "fdk_circular_matrices", "fdk_phantom_project", "fdk_bp_plan",
            "fdk_last_error", "fdk_status_string",
            "fdk_cosine_weight", "fdk_conv1d_forward", "fdk_conv1d_backward_data",
-           "fdk_conv1d_backward_weight", "fdk_sqerr", "fdk_adam")
+           "fdk_conv1d_backward_weight", "fdk_sqerr", "fdk_adam",
+           "fdk_backproject_variant")
 
 
 def check(code: int) -> None:

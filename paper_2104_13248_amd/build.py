@@ -31,7 +31,8 @@ DEVICE = ["-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-op
           "-munsafe-fp-atomics"]
 
 SOURCES = ["api.cpp", "geometry.cpp", "runtime.cpp", "compose.hip", "bp.hip", "fp.hip",
-           "filter.hip", "quantize.hip", "phantom.hip", "learn.hip"]
+           "filter.hip", "quantize.hip", "phantom.hip", "learn.hip",
+           "ablation.hip"]
 HEADERS = ["internal.h", "footprint.h"]
 
 

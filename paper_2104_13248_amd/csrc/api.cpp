@@ -342,3 +342,54 @@ extern "C" fdk_status fdk_adam(int32_t n, float* p, const float* g, float* m, fl
         return fail(FDK_E_INVALID, "Adam needs 0 <= beta < 1, eps > 0, finite lr");
     return launch_adam(n, p, g, m, v, lr, beta1, beta2, eps, t, stream);
 }
+
+// ---------------------------------------------------------------- back-projection variants
+
+#include "fdk_ablation.h"
+
+extern "C" fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const fdk_volume* vg,
+                                              float* vol, const fdk_stack* sg, const float* proj,
+                                              const double* mats, void* stream)
+{
+    std::vector<IndexMatrix> M;
+    fdk_status s = common_checks(vg, sg, false, mats, &M);
+    if (s != FDK_OK) return s;
+    if (!vol || !proj) return fail(FDK_E_INVALID, "volume/projection pointer is NULL");
+    if (nb < 1) return fail(FDK_E_INVALID, "nb must be at least 1");
+    if (variant != FDK_VARIANT_PRODUCTION && variant != FDK_VARIANT_GLOBAL_TAPS &&
+        variant != FDK_VARIANT_LISTING1)
+        return fail(FDK_E_INVALID, "unknown back-projection variant");
+    const int32_t batch = nb < sg->np ? nb : sg->np;
+    if (variant == FDK_VARIANT_PRODUCTION) {
+        const size_t view = (size_t)sg->nh * sg->nw;
+        for (int32_t s0 = 0; s0 < sg->np; s0 += batch) {
+            fdk_stack sub = *sg;
+            sub.np = s0 + batch < sg->np ? batch : sg->np - s0;
+            s = fdk_backproject(vg, vol, &sub, proj + (size_t)s0 * view, nullptr,
+                                mats + 12 * (size_t)s0, stream);
+            if (s != FDK_OK) return s;
+        }
+        return FDK_OK;
+    }
+    const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
+    void* d_world = nullptr;
+    void* d_index = nullptr;
+    s = upload_async(mats, mbytes, stream, &d_world);
+    if (s == FDK_OK) s = device_alloc_async(mbytes, stream, &d_index);
+    if (s == FDK_OK) {
+        double ox, oy, oz;
+        fill_grid(*vg, ox, oy, oz);
+        s = launch_compose((const double*)d_world, (double*)d_index, sg->np, vg->dx, vg->dy, vg->dz,
+                           ox, oy, oz, stream);
+    }
+    if (s == FDK_OK)
+        s = launch_backproject_variant(variant, batch, proj, (const double*)d_index, vol, vg->nx,
+                                       vg->ny, vg->nz, sg->np, sg->nh, sg->nw, stream);
+    fdk_status s2 = FDK_OK;
+    for (void* d : {d_index, d_world})
+        if (d) {
+            fdk_status e = device_free_async(d, stream);
+            if (s2 == FDK_OK) s2 = e;
+        }
+    return s != FDK_OK ? s : s2;
+}

@@ -136,6 +136,12 @@ fdk_status launch_conv1d_backward_weight(int cin, int cout, int rows, int len, c
                                          const float* gout, float* gw, float* gb, void* stream);
 fdk_status launch_sqerr(int64_t n, const float* a, const float* b, float* grad, float scale,
                         float* loss, void* stream);
+// Back-projection variants of include/fdk_ablation.h (float32 projections;
+// mats_index: device [np][12] composed index-space matrices).
+fdk_status launch_backproject_variant(int variant, int nb, const float* proj,
+                                      const double* mats_index, float* vol, int nx, int ny,
+                                      int nz, int np, int nh, int nw, void* stream);
+
 fdk_status launch_adam(int n, float* p, const float* g, float* m, float* v, float lr, float b1,
                        float b2, float eps, int step, void* stream);
 

@@ -273,3 +273,17 @@ def test_learned_filter_entry_points_validate():
     bad = _lib.stack_struct(2, 3, 4, _lib.FDK_F16)
     assert lib.fdk_cosine_weight(ctypes.byref(bad), FAKE, FAKE, 1.0, 1.0, 100.0, 0.0, 0.0,
                                  None) != OK
+
+
+def test_variant_entry_point_validates():
+    vg, sg, m = _geom(C1)
+    lib = _lib.lib
+    assert lib.fdk_backproject_variant(9, 4, ctypes.byref(vg), FAKE, ctypes.byref(sg), FAKE,
+                                       _lib.ptr(m), None) == E_INVALID
+    assert lib.fdk_backproject_variant(2, 0, ctypes.byref(vg), FAKE, ctypes.byref(sg), FAKE,
+                                       _lib.ptr(m), None) == E_INVALID
+    assert lib.fdk_backproject_variant(1, 4, ctypes.byref(vg), None, ctypes.byref(sg), FAKE,
+                                       _lib.ptr(m), None) == E_INVALID
+    s16 = _lib.stack_struct(C1["np"], C1["nh"], C1["nw"], _lib.FDK_F16)
+    assert lib.fdk_backproject_variant(1, 4, ctypes.byref(vg), FAKE, ctypes.byref(s16), FAKE,
+                                       _lib.ptr(m), None) == E_UNSUPPORTED

@@ -36,6 +36,10 @@ OPS_PER_UPDATE = 10
 # FP32 VALU lane-operations.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+# On-chip gather bound: LDS delivers 128 bytes per clock per CU; an update
+# reads its four taps from LDS, 16 bytes as float32 or 8 bytes as two
+# binary16 pair words.
+LDS_BYTES_PER_CLK_CU = 128
 # Calibration copy for the HBM byte counters: a plain device-to-device copy of
 # this many bytes, run once when --calibrate-copy is given.
 CALIBRATION_BYTES = 1 << 30
@@ -212,6 +216,7 @@ def main() -> int:
     achieved = n_upd * OPS_PER_UPDATE / k_s / 1e12
     vol_bytes = nx * ny * nz * 4
     hbm_alg = 2 * vol_bytes + npv * nh * nw * 2 + npv * 4           # volume RMW + f16 stack
+    lds_bound = 256 * 2.4e9 * LDS_BYTES_PER_CLK_CU / 8 / 1e9      # FP16 storage: 8 B/update
     workload = "fdk_backprojection_%dx%dx%d_%dviews_%dx%d" % (nx, ny, nz, npv, nh, nw)
     traffic = measured_traffic(workload)
     out = {
@@ -243,7 +248,9 @@ def main() -> int:
                      "ops_per_update": OPS_PER_UPDATE,
                      "hbm_algorithmic_bytes": hbm_alg,
                      "hbm_algorithmic_gbs": hbm_alg / k_s / 1e9,
-                     "hbm_frac": hbm_alg / k_s / 1e9 / HBM_PEAK_GBS},
+                     "hbm_frac": hbm_alg / k_s / 1e9 / HBM_PEAK_GBS,
+                     "lds_gather_bound_gups": lds_bound,
+                     "lds_gather_frac": f16["kernel_gups"] / lds_bound},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, np.asarray(mats), args.cpu_seconds)

@@ -210,6 +210,28 @@ def test_c3_full_size_sampled_f16():
     assert e <= TOL32
 
 
+def test_p10_1300cube_sampled():
+    """The paper's largest problem (Table 3, P10: 1024^2 x 512 views =>
+    1300^3, 8.2 GiB of volume), float32: ragged tiles (1300 = 81 x 16 + 4) and
+    a ragged last chunk of slices; sampled voxels against the oracle."""
+    from paper_2104_13248_amd import problems
+    shape, voxel, mats, nh, nw = problems.geometry("P10")
+    npv = problems.VIEWS
+    log("p10: generating", (npv, nh, nw))
+    proj = wl.gaussian(10010, (npv, nh, nw))
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    p = torch.from_numpy(proj).cuda()
+    fdk.backproject(vol, p, mats, voxel)
+    torch.cuda.synchronize()
+    ijk = _sample_voxels(shape, 384, 13)
+    got = vol[ijk[:, 2], ijk[:, 1], ijk[:, 0]].cpu().numpy()
+    del vol, p
+    ref = oracle.backproject_points(proj, mats, shape, voxel, ijk)
+    e = rel(got, ref)
+    log("p10 sampled rel-L2", e)
+    assert e <= TOL32
+
+
 # Strongly magnified cone geometries: some blocks' footprints are taller than
 # the LDS tile and are staged per half-chunk.
 SPLIT = [

@@ -81,18 +81,59 @@ struct BpArgs {
     int rows;                 // LDS rows allocated
 };
 
-// Stage rows [r0, r0+R) x columns [c0, c0+C) of one view into the LDS tile
-// (row pitch PITCH words), zero outside the detector.  Wave w stages rows w, w+4, ...; lanes run along the row.  One
-// buffer descriptor covers the view; a column outside the detector gets an
-// out-of-range offset (reads as zero), a row outside it is written as zeros.
+// Words per LDS row: float32 rows hold PITCH pixels; binary16 rows are two
+// regions of pair-word half-rows (even and odd offsets), PITCH / 2 words each.
 template <int PITCH, bool F16>
-__device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rsrc_t& rs, int nh,
-                                           unsigned row_bytes, int nw, int r0, int c0, int R, int C,
-                                           int wave, int lane)
+struct TileRow {
+    static constexpr int W = F16 ? PITCH / 2 : PITCH;
+};
+
+// Stage rows [r0, r0+R) x columns [c0, c0+C) of one view into the LDS tile,
+// zero outside the detector.  One buffer descriptor covers the view; an
+// out-of-range offset reads as zero.  The tile has `ralloc` rows of
+// TileRow::W words (float32), or two such regions (binary16: even-offset
+// pairs, then odd-offset pairs).
+//
+// A window inside the detector's columns is staged by 16-byte loads straight
+// into LDS, whole rows at a time: a row of W words takes W / 4 lanes, so one
+// instruction stages 64 / (W / 4) rows and the lanes of a row land side by
+// side.  Other windows are staged by 4-byte loads: lanes along a row, wave w
+// taking rows w, w + 4, ...
+template <int PITCH, bool F16>
+__device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdgpu_buffer_rsrc_t& rs,
+                                           int nh, unsigned row_bytes, int nw, int r0, int c0, int R,
+                                           int C, int wave, int lane)
 {
     constexpr int kWaves = kThreads / 64;
     constexpr unsigned kOut = 0x80000000u;   // beyond any view: the load returns zero
+    constexpr int RW = TileRow<PITCH, F16>::W;
+    constexpr int SEG = RW / 4;               // 16-byte lanes per row
+    constexpr int RPI = 64 / SEG;             // rows per instruction
+    static_assert(RW % 4 == 0 && RPI >= 1, "row width");
     unsigned* wtile = reinterpret_cast<unsigned*>(tile);
+    {
+        const int cs = F16 ? (c0 & ~1) : c0;                  // first staged pixel
+        const int span = F16 ? 8 * SEG + 1 : 4 * SEG;         // pixels a row's loads read
+        if (cs >= 0 && cs + span <= nw) {
+            const int rsub = lane / SEG, sg = lane - rsub * SEG;
+            const unsigned colb = (unsigned)cs * (F16 ? 2u : 4u) + 16u * (unsigned)sg;
+            for (int rr0 = wave * RPI; rr0 < R; rr0 += kWaves * RPI) {
+                const int rr = rr0 + rsub;
+                if (rsub < RPI && rr < R) {
+                    const int r = r0 + rr;
+                    const unsigned vo = (unsigned)r < (unsigned)nh ? (unsigned)r * row_bytes + colb : kOut;
+                    lds_void* d = (lds_void*)(size_t)lds_addr(tile + rr0 * RW);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, vo, 0, 0, 0);
+                    if (F16) {
+                        lds_void* d2 = (lds_void*)(size_t)lds_addr(tile + (ralloc + rr0) * RW);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d2, 16, vo == kOut ? kOut : vo + 2u,
+                                                                 0, 0, 0);
+                    }
+                }
+            }
+            return;
+        }
+    }
     if (!F16) {
         for (int g = 0; g * 64 < C; ++g) {
             const int cc = g * 64 + lane;
@@ -113,10 +154,10 @@ __device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rs
             }
         }
     } else {
-        // Binary16 rows are staged as two half-rows of pair words by
-        // asynchronous dword loads straight into LDS: EV[m] holds pixels
-        // (ce+2m, ce+2m+1) (aligned loads) and OD[m] pixels (ce+2m+1, ce+2m+2)
-        // (2-byte aligned loads), ce = c0 rounded down to even.  The pair
+        // Binary16 rows are staged as pair words by asynchronous dword loads
+        // straight into LDS: EV[m] holds pixels (ce+2m, ce+2m+1) (aligned
+        // loads) and OD[m] pixels (ce+2m+1, ce+2m+2) (2-byte aligned loads),
+        // ce = c0 rounded down to even, in two regions of half-rows.  The pair
         // (p[c], p[c+1]) of column c is EV[(c-ce)/2] or OD[(c-ce-1)/2].  A word
         // with one pixel outside the detector is rewritten afterwards from a
         // 16-bit load of its valid pixel.
@@ -134,14 +175,14 @@ __device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rs
                 const int r = r0 + rr;
                 if ((unsigned)r < (unsigned)nh) {
                     if (keep) {
-                        lds_void* de = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + g * 64);
-                        lds_void* dd = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + HP + g * 64);
+                        lds_void* de = (lds_void*)(size_t)lds_addr(tile + rr * HP + g * 64);
+                        lds_void* dd = (lds_void*)(size_t)lds_addr(tile + (ralloc + rr) * HP + g * 64);
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, de, 4, voe, (unsigned)r * row_bytes, 0, 0);
                         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, dd, 4, voo, (unsigned)r * row_bytes, 0, 0);
                     }
                 } else if (keep) {
-                    wtile[rr * PITCH + mm] = 0u;
-                    wtile[rr * PITCH + HP + mm] = 0u;
+                    wtile[rr * HP + mm] = 0u;
+                    wtile[(ralloc + rr) * HP + mm] = 0u;
                 }
             }
         }
@@ -159,12 +200,12 @@ __device__ __forceinline__ void stage_rows(float* tile, const __amdgpu_buffer_rs
                 if ((unsigned)r >= (unsigned)nh) continue;
                 if (fix_left && lane == 0) {
                     const unsigned p0 = __builtin_amdgcn_raw_buffer_load_b16(rs, 0u, (unsigned)r * row_bytes, 0);
-                    wtile[rr * PITCH + HP + mleft] = p0 << 16;
+                    wtile[(ralloc + rr) * HP + mleft] = p0 << 16;
                 }
                 if (fix_right && lane == 1) {
                     const unsigned pl = __builtin_amdgcn_raw_buffer_load_b16(
                         rs, (unsigned)(nw - 1) * 2u, (unsigned)r * row_bytes, 0);
-                    wtile[rr * PITCH + (right_od ? HP : 0) + mright] = pl;
+                    wtile[((right_od ? ralloc : 0) + rr) * HP + mright] = pl;
                 }
             }
         }
@@ -189,12 +230,13 @@ __device__ __forceinline__ void update_half(float (&acc)[KZ], int k0, unsigned b
             const float v = fmaf((float)(g0 + q), dv, v0);
             fv[q] = __builtin_amdgcn_fractf(v);
             // row floor(v) (v >= 1 inside the tile): one 24-bit multiply-add
-            const lds_u32* p = (const lds_u32*)(size_t)(__umul24((unsigned)(int)v, 4u * PITCH) + base);
+            constexpr int RW = TileRow<PITCH, F16>::W;
+            const lds_u32* p = (const lds_u32*)(size_t)(__umul24((unsigned)(int)v, 4u * RW) + base);
             t[q][0] = p[0];
-            t[q][2] = p[PITCH];
+            t[q][2] = p[RW];
             if (!F16) {
                 t[q][1] = p[1];
-                t[q][3] = p[PITCH + 1];
+                t[q][3] = p[RW + 1];
             }
         }
 #pragma unroll
@@ -267,7 +309,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 (void*)(proj + (size_t)(sb + qv) * view_bytes), 0, (int)view_bytes, kBufferFlags);
             // ---- stage the footprint of view sb+qv (zero outside the detector)
-            stage_rows<PITCH, F16>(tile, rs, A.nh, row_bytes, A.nw, uniform(rv.r0), c0,
+            stage_rows<PITCH, F16>(tile, A.rows, rs, A.nh, row_bytes, A.nw, uniform(rv.r0), c0,
                                    uniform(rv.R), C, wave, lane);
             __builtin_amdgcn_s_waitcnt(0);                    // this wave's LDS writes landed
             __syncthreads();
@@ -280,12 +322,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             const float W = F * F * uniform(rv.scale);
             const float fu = __builtin_amdgcn_fractf(u);
             // LDS byte address of the pair word of column floor(u) in tile row 0
-            // (u >= 1 inside the tile); binary16 rows hold even- and odd-offset
-            // pairs in two half-rows
+            // (u >= 1 inside the tile); binary16 tiles hold even- and odd-offset
+            // pairs in two regions
             unsigned base;
             if (F16) {
                 const int j = (int)u + (uniform(rv.c0) & 1);
-                base = tile_base + 4u * (unsigned)((j >> 1) + ((j & 1) ? PITCH / 2 : 0));
+                base = tile_base + 4u * (unsigned)((j >> 1) + ((j & 1) ? A.rows * (PITCH / 2) : 0));
             } else {
                 base = tile_base + 4u * (unsigned)(int)u;
             }
@@ -295,14 +337,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             for (int q = 0; q < 2; ++q) {
                 if (q == 1 && uniform(rv.split)) {
                     __syncthreads();
-                    stage_rows<PITCH, F16>(tile, rs, A.nh, row_bytes, A.nw, uniform(rv.r1), c0,
-                                           uniform(rv.R1), C, wave, lane);
+                    stage_rows<PITCH, F16>(tile, A.rows, rs, A.nh, row_bytes, A.nw, uniform(rv.r1),
+                                           c0, uniform(rv.R1), C, wave, lane);
                     __builtin_amdgcn_s_waitcnt(0);
                     __syncthreads();
                 }
                 const HalfBase& hb = rv.half[q];
                 const float v0 = fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
-                const unsigned row_base = base + (unsigned)(uniform(hb.row) * 4 * PITCH);
+                const unsigned row_base =
+                    base + (unsigned)(uniform(hb.row) * 4 * TileRow<PITCH, F16>::W);
                 update_half<KZ, PITCH, F16>(acc, q * (KZ / 2), row_base, v0, dv, fu, W);
             }
             __syncthreads();                                  // tile is overwritten next

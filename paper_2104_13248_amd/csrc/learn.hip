@@ -135,6 +135,133 @@ __global__ __launch_bounds__(ConvShape<COUT>::NT) void conv_kernel(
     }
 }
 
+// 32 -> 32 channels on the matrix cores (v_mfma_f32_16x16x4f32: FP32
+// products, FP32 accumulation).  The layer is a contraction over
+// K = 32 channels x 9 taps per output: out[o][x] = sum_k A[o][k] B[k][x], with
+// k = 32 t + i so that each 4-wide step of K covers 4 input channels at one
+// tap; B[k][x] = in[i][x + t - 4] is then a fixed per-lane LDS offset plus a
+// wave-uniform step offset.  Forward: A[o][k] = w[o][i][t]; transposed
+// (backward data): A[o][k] = w[i][o][8 - t] (o, i the roles of the computed
+// convolution).  The A operands are laid out once per call in the order the
+// lanes read them (wa[o-tile][step][lane]), so every block reads them as
+// coalesced, cache-resident loads.  Block: one row segment of 256 positions,
+// all 32 input channels staged in LDS, 4 waves x 64 positions x 32 output
+// channels (2 x 4 tiles of 16 x 16).
+constexpr int kMxSeg = 256;                     // positions per block
+// LDS pitch of a staged channel: = 16 (mod 64), so the 4 channels x 16
+// positions a B operand reads fall in distinct banks
+constexpr int kMxTP = kMxSeg + 2 * kHalo + 8;
+constexpr int kMxSteps = 32 / 4 * kK;           // K steps (72)
+
+typedef float mx4 __attribute__((ext_vector_type(4)));
+
+// A operands in the order one half of the input channels reads them:
+// wa[h][ot][j][l] = A[ot*16 + l%16][k], k = 32 t + 16 h + 4 q + l/16, j = 4 t + q
+// (t the tap, q the channel quad within the half).
+template <bool TRANS>
+__global__ void arrange_a_kernel(const float* __restrict__ w, float* __restrict__ wa)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * kMxSteps * 64) return;
+    const int l = idx & 63, j = (idx >> 6) % (kMxSteps / 2);
+    const int ot = (idx / (64 * (kMxSteps / 2))) & 1, h = idx / (64 * kMxSteps);
+    const int t = j >> 2, q = j & 3;
+    const int o = ot * 16 + (l & 15), i = 16 * h + 4 * q + (l >> 4);
+    wa[idx] = TRANS ? w[((size_t)i * 32 + o) * kK + (kK - 1 - t)] : w[((size_t)o * 32 + i) * kK + t];
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ lds_void_t* lds_ptr(const void* p)
+{
+    return (lds_void_t*)(size_t)(unsigned)(size_t)(__attribute__((address_space(3))) const char*)p;
+}
+
+__global__ __launch_bounds__(256) void conv32_mfma_kernel(const float* __restrict__ in,
+                                                        const float* __restrict__ wa,
+                                                        const float* __restrict__ bias,
+                                                        const float* __restrict__ mask,
+                                                        const float* add, float alpha, int relu,
+                                                        float* out, int len, int nseg)
+{
+    // input channels in two halves of 16; each half's A operands (36 steps x 2
+    // o-tiles x 64 lanes) are staged in LDS beside its input samples
+    __shared__ float tile[16][kMxTP];
+    __shared__ float la[2][kMxSteps / 2][64];
+    const int r = blockIdx.x / nseg;
+    const int x0 = (blockIdx.x - r * nseg) * kMxSeg;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const float* src = in + (size_t)r * 32 * len;
+    mx4 acc[2][4];
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int xt = 0; xt < 4; ++xt) acc[ot][xt] = mx4{0.f, 0.f, 0.f, 0.f};
+    // per-lane part of the B address: channel l/16 of the step, position l%16
+    const float* tl = &tile[0][0] + (lane >> 4) * kMxTP + wave * 64 + (lane & 15);
+    // the block's input rows and the A operands go straight from memory into
+    // LDS (asynchronous buffer loads; samples outside the row read as zero)
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)src, 0, (int)(32u * (unsigned)len * 4u), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rwa = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)wa, 0, 2 * kMxSteps * 64 * 4, 0x00020000);
+    constexpr unsigned kOut = 0x80000000u;
+    for (int h = 0; h < 2; ++h) {
+        __syncthreads();                                   // previous half no longer read
+        for (int g = 0; g * 64 < kMxSeg + 2 * kHalo; ++g) {
+            const int xx = g * 64 + lane;
+            const int x = x0 + xx - kHalo;
+            const unsigned vo = (x >= 0 && x < len) ? (unsigned)x * 4u : kOut;
+            if (xx < kMxSeg + 2 * kHalo) {                  // lanes past the row write nothing
+                for (int ci = wave; ci < 16; ci += 4) {
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rin, lds_ptr(&tile[ci][g * 64]), 4, vo,
+                        (unsigned)(16 * h + ci) * (unsigned)len * 4u, 0, 0);
+                }
+            }
+        }
+        for (int q = wave; q * 64 < kMxSteps * 64; q += 4)          // 36 x 2 rows of 64 lanes
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rwa, lds_ptr(&la[0][0][0] + q * 64), 4,
+                                                     (unsigned)lane * 4u,
+                                                     (unsigned)(h * kMxSteps * 64 + q * 64) * 4u, 0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll 4
+        for (int j = 0; j < kMxSteps / 2; ++j) {
+            const int t = j >> 2, quad = j & 3;
+            const float a0 = la[0][j][lane], a1 = la[1][j][lane];
+            const float* tb = tl + 4 * quad * kMxTP + t;
+#pragma unroll
+            for (int xt = 0; xt < 4; ++xt) {
+                const float b = tb[16 * xt];
+                acc[0][xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b, acc[0][xt], 0, 0, 0);
+                acc[1][xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b, acc[1][xt], 0, 0, 0);
+            }
+        }
+    }
+    // D: lane l, register q -> channel ot*16 + 4 (l/16) + q, position l%16 of the tile
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+        for (int xt = 0; xt < 4; ++xt) {
+            const int x = x0 + wave * 64 + 16 * xt + (lane & 15);
+            if (x < len) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int o = ot * 16 + 4 * (lane >> 4) + q;
+                    const size_t oc = ((size_t)r * 32 + o) * len + x;
+                    float y = acc[ot][xt][q] + (bias ? bias[o] : 0.f);
+                    if (relu) y = fmaxf(y, 0.f);
+                    if (mask && !(mask[oc] > 0.f)) y = 0.f;
+                    y *= alpha;
+                    if (add) y += add[oc];
+                    out[oc] = y;
+                }
+            }
+        }
+}
+
 // grad_w[o][i][t] += sum_{r,x} gout[r][o][x] in[r][i][x + t - k/2]
 // grad_b[o]       += sum_{r,x} gout[r][o][x]
 // Thread (pair, s) owns NPT (o, i) pairs with their k taps and the s-th of
@@ -288,6 +415,30 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
     p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
 }
 
+template <bool TRANS>
+fdk_status conv32(int rows, int len, const float* in, const float* w, const float* b,
+                  const float* mask, const float* add, float alpha, int relu, float* out,
+                  hipStream_t st)
+{
+    const int nseg = (len + kMxSeg - 1) / kMxSeg;
+    if ((int64_t)nseg * rows >= (1ll << 31) || (int64_t)len * 32 * 4 >= (1ll << 31))
+        return fail(FDK_E_UNSUPPORTED, "conv1d tensor too large for one launch");
+    void* wa = nullptr;
+    constexpr int n = 2 * kMxSteps * 64;
+    fdk_status s = device_alloc_async(n * sizeof(float), st, &wa);
+    if (s != FDK_OK) return s;
+    hipLaunchKernelGGL(arrange_a_kernel<TRANS>, dim3((n + 255) / 256), dim3(256), 0, st, w,
+                       (float*)wa);
+    s = check_launch("weight layout kernel");
+    if (s == FDK_OK) {
+        hipLaunchKernelGGL(conv32_mfma_kernel, dim3((unsigned)(nseg * rows)), dim3(256), 0, st, in,
+                           (const float*)wa, b, mask, add, alpha, relu, out, len, nseg);
+        s = check_launch(TRANS ? "conv1d backward-data kernel" : "conv1d forward kernel");
+    }
+    const fdk_status s2 = device_free_async(wa, st);
+    return s != FDK_OK ? s : s2;
+}
+
 template <int CIN, int COUT, bool TRANS>
 fdk_status conv(int rows, int len, const float* in, const float* w, const float* b,
                 const float* mask, const float* add, float alpha, int relu, float* out,
@@ -331,7 +482,7 @@ fdk_status launch_conv1d_forward(int cin, int cout, int rows, int len, const flo
     if (!supported(cin, cout))
         return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
     if (cin == 1 && cout == 32) return conv<1, 32, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
-    if (cin == 32 && cout == 32) return conv<32, 32, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    if (cin == 32 && cout == 32) return conv32<false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
     if (cin == 32 && cout == 1) return conv<32, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
     return conv<1, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
 }
@@ -344,7 +495,7 @@ fdk_status launch_conv1d_backward_data(int cin, int cout, int rows, int len, con
         return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
     // the transposed convolution reads `cout` channels and writes `cin`
     if (cin == 1 && cout == 32) return conv<32, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
-    if (cin == 32 && cout == 32) return conv<32, 32, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    if (cin == 32 && cout == 32) return conv32<true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
     if (cin == 32 && cout == 1) return conv<1, 32, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
     return conv<1, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
 }

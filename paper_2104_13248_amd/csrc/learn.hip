@@ -135,6 +135,152 @@ __global__ __launch_bounds__(ConvShape<COUT>::NT) void conv_kernel(
     }
 }
 
+// Layers with one input or one output channel move 32 channels of
+// activations per position against at most 9 x 32 multiply-adds, so they are
+// bound by memory, not arithmetic.  Each thread owns 4 consecutive positions
+// of one row and streams what it needs straight from memory (16-byte loads
+// where the row allows; neighbouring threads share the 4-sample halos through
+// the cache): nothing is staged, few registers are live and many waves stay
+// resident to cover the memory latency.
+
+// Whether every base pointer allows 16-byte accesses (with len % 4 == 0,
+// then so does every row).
+__device__ __forceinline__ bool aligned16(const float* a, const float* b, const float* c,
+                                          const float* d)
+{
+    return (((size_t)a | (size_t)b | (size_t)c | (size_t)d) & 15) == 0;
+}
+
+// Samples in[x0 - 4 .. x0 + 7] of one channel row, zero outside [0, len).
+__device__ __forceinline__ void load12(const float* __restrict__ row, int x0, int len, bool vec,
+                                       float (&v)[12])
+{
+    if (vec) {
+        const float4 a = *reinterpret_cast<const float4*>(row + x0 - 4);
+        const float4 b = *reinterpret_cast<const float4*>(row + x0);
+        const float4 c = *reinterpret_cast<const float4*>(row + x0 + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+        v[8] = c.x; v[9] = c.y; v[10] = c.z; v[11] = c.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            const int x = x0 - 4 + e;
+            v[e] = (x >= 0 && x < len) ? row[x] : 0.f;
+        }
+    }
+}
+
+// Epilogue of one output channel's 4 positions (the layer kernel's order:
+// bias already in acc; ReLU, mask, alpha, residual addend).
+__device__ __forceinline__ void store4(float (&acc)[4], size_t oc, int x0, int len, bool vec4,
+                                       const float* __restrict__ mask, const float* add, float alpha,
+                                       int relu, float* out)
+{
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        float y = acc[p];
+        if (relu) y = fmaxf(y, 0.f);
+        acc[p] = y;
+    }
+    if (vec4) {
+        if (mask) {
+            const float4 m = *reinterpret_cast<const float4*>(mask + oc);
+            if (!(m.x > 0.f)) acc[0] = 0.f;
+            if (!(m.y > 0.f)) acc[1] = 0.f;
+            if (!(m.z > 0.f)) acc[2] = 0.f;
+            if (!(m.w > 0.f)) acc[3] = 0.f;
+        }
+        float4 y = make_float4(acc[0] * alpha, acc[1] * alpha, acc[2] * alpha, acc[3] * alpha);
+        if (add) {
+            const float4 a = *reinterpret_cast<const float4*>(add + oc);
+            y.x += a.x; y.y += a.y; y.z += a.z; y.w += a.w;
+        }
+        *reinterpret_cast<float4*>(out + oc) = y;
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            if (x0 + p < len) {
+                float y = acc[p];
+                if (mask && !(mask[oc + p] > 0.f)) y = 0.f;
+                y *= alpha;
+                if (add) y += add[oc + p];
+                out[oc + p] = y;
+            }
+        }
+    }
+}
+
+// 32 channels -> 1: the last layer's forward, or (TRANS) the first layer's
+// backward-data pass (weights w[32][1][k], taps mirrored).
+template <bool TRANS>
+__global__ __launch_bounds__(256) void conv_to1_kernel(const float* __restrict__ in,
+                                                       const float* __restrict__ w,
+                                                       const float* __restrict__ bias,
+                                                       const float* __restrict__ mask,
+                                                       const float* add, float alpha, int relu,
+                                                       float* out, int rows, int len, int nq)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)rows * nq) return;
+    const int r = (int)(g / nq);
+    const int x0 = 4 * (int)(g - (int64_t)r * nq);
+    const bool al = aligned16(in, out, mask, add) && (len & 3) == 0;
+    const bool vec = al && x0 >= 4 && x0 + 8 <= len;
+    const float* src = in + (size_t)r * 32 * len;
+    float acc[4];
+    const float b0 = bias ? bias[0] : 0.f;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) acc[p] = b0;
+#pragma unroll 4
+    for (int i = 0; i < 32; ++i) {
+        float v[12];
+        load12(src + (size_t)i * len, x0, len, vec, v);
+#pragma unroll
+        for (int t = 0; t < kK; ++t) {
+            const float wt = TRANS ? w[i * kK + (kK - 1 - t)] : w[i * kK + t];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[p] = fmaf(wt, v[p + t], acc[p]);
+        }
+    }
+    store4(acc, (size_t)r * len + x0, x0, len, al && x0 + 4 <= len, mask, add, alpha, relu, out);
+}
+
+// 1 channel -> 32: the first layer's forward, or (TRANS) the last layer's
+// backward-data pass (weights w[1][32][k], taps mirrored).
+template <bool TRANS>
+__global__ __launch_bounds__(256) void conv_from1_kernel(const float* __restrict__ in,
+                                                         const float* __restrict__ w,
+                                                         const float* __restrict__ bias,
+                                                         const float* __restrict__ mask,
+                                                         const float* add, float alpha, int relu,
+                                                         float* out, int rows, int len, int nq)
+{
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)rows * nq) return;
+    const int r = (int)(g / nq);
+    const int x0 = 4 * (int)(g - (int64_t)r * nq);
+    const bool al = aligned16(in, out, mask, add) && (len & 3) == 0;
+    const bool vec = al && x0 >= 4 && x0 + 8 <= len;
+    const bool vec4 = al && x0 + 4 <= len;
+    float v[12];
+    load12(in + (size_t)r * len, x0, len, vec, v);
+#pragma unroll 2
+    for (int o = 0; o < 32; ++o) {
+        float acc[4];
+        const float b0 = bias ? bias[o] : 0.f;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) acc[p] = b0;
+#pragma unroll
+        for (int t = 0; t < kK; ++t) {
+            const float wt = TRANS ? w[o * kK + (kK - 1 - t)] : w[o * kK + t];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[p] = fmaf(wt, v[p + t], acc[p]);
+        }
+        store4(acc, ((size_t)r * 32 + o) * len + x0, x0, len, vec4, mask, add, alpha, relu, out);
+    }
+}
+
 // 32 -> 32 channels on the matrix cores (v_mfma_f32_16x16x4f32: FP32
 // products, FP32 accumulation).  The layer is a contraction over
 // K = 32 channels x 9 taps per output: out[o][x] = sum_k A[o][k] B[k][x], with
@@ -439,6 +585,24 @@ fdk_status conv32(int rows, int len, const float* in, const float* w, const floa
     return s != FDK_OK ? s : s2;
 }
 
+// Launch of the streaming kernels (TO1: 32 -> 1, else 1 -> 32).
+template <bool TO1, bool TRANS>
+fdk_status conv_stream(int rows, int len, const float* in, const float* w, const float* b,
+                       const float* mask, const float* add, float alpha, int relu, float* out,
+                       hipStream_t st)
+{
+    const int nq = (len + 3) / 4;
+    const int64_t blocks = ((int64_t)rows * nq + 255) / 256;
+    if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "conv1d tensor too large for one launch");
+    if (TO1)
+        hipLaunchKernelGGL(conv_to1_kernel<TRANS>, dim3((unsigned)blocks), dim3(256), 0, st, in, w, b,
+                           mask, add, alpha, relu, out, rows, len, nq);
+    else
+        hipLaunchKernelGGL(conv_from1_kernel<TRANS>, dim3((unsigned)blocks), dim3(256), 0, st, in, w,
+                           b, mask, add, alpha, relu, out, rows, len, nq);
+    return check_launch(TRANS ? "conv1d backward-data kernel" : "conv1d forward kernel");
+}
+
 template <int CIN, int COUT, bool TRANS>
 fdk_status conv(int rows, int len, const float* in, const float* w, const float* b,
                 const float* mask, const float* add, float alpha, int relu, float* out,
@@ -481,9 +645,9 @@ fdk_status launch_conv1d_forward(int cin, int cout, int rows, int len, const flo
     hipStream_t st = (hipStream_t)stream;
     if (!supported(cin, cout))
         return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
-    if (cin == 1 && cout == 32) return conv<1, 32, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    if (cin == 1 && cout == 32) return conv_stream<false, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
     if (cin == 32 && cout == 32) return conv32<false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
-    if (cin == 32 && cout == 1) return conv<32, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
+    if (cin == 32 && cout == 1) return conv_stream<true, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
     return conv<1, 1, false>(rows, len, in, w, bias, mask, add, alpha, relu, out, st);
 }
 
@@ -494,9 +658,9 @@ fdk_status launch_conv1d_backward_data(int cin, int cout, int rows, int len, con
     if (!supported(cin, cout))
         return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
     // the transposed convolution reads `cout` channels and writes `cin`
-    if (cin == 1 && cout == 32) return conv<32, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    if (cin == 1 && cout == 32) return conv_stream<true, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
     if (cin == 32 && cout == 32) return conv32<true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
-    if (cin == 32 && cout == 1) return conv<1, 32, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
+    if (cin == 32 && cout == 1) return conv_stream<false, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
     return conv<1, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
 }
 

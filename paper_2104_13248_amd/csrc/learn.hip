@@ -524,6 +524,230 @@ __global__ __launch_bounds__(kCT) void conv_wgrad_kernel(const float* __restrict
     }
 }
 
+// Weight gradient of a 32 -> 32 layer on the matrix cores: for each block's
+// run of positions, G[o][n] = sum_x gout[o][x] in[i][x + t - k/2] with
+// n = 9 i + t (the column order of w[o][i][t]), i.e. a 32 x 288 contraction
+// over positions, 4 positions per v_mfma_f32_16x16x4f32 step.  A block owns
+// every 1024th work item (one row segment of 128 positions), staged with
+// asynchronous loads straight into LDS; wave w accumulates the 16 x 16 tiles
+// (o tile w % 2, n tiles 9 (w / 2) .. 9 (w / 2) + 8) in registers across all
+// its items, then writes the block's partial sums (and its bias partial
+// sums); a second kernel adds the partials of all blocks in a fixed order, so
+// the result does not depend on scheduling.
+constexpr int kWgSeg = 128;                       // positions per work item
+constexpr int kWgTP = kWgSeg + 2 * kHalo + 4;     // input row pitch (140 = 12 mod 32)
+constexpr int kWgGP = kWgSeg + 4;                 // gradient row pitch (132 = 4 mod 32)
+constexpr int kWgN = 32 * kK;                     // 288 columns
+constexpr int kWgPart = 32 * kWgN + 32;           // floats of one block's partial sums
+constexpr int kWgBlocks = 1024;
+
+__global__ __launch_bounds__(256) void wgrad32_mfma_kernel(const float* __restrict__ in,
+                                                         const float* __restrict__ go,
+                                                         float* __restrict__ part, int rows,
+                                                         int len, int nseg)
+{
+    __shared__ float tin[32][kWgTP];
+    __shared__ float tgo[32][kWgGP];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ot = wave & 1, nt0 = (wave >> 1) * 9;
+    // per-lane LDS offsets: A[o][k] = gout[o][x + k], B[k][n] = in[i][x + k + t - k/2]
+    const int aoff = (ot * 16 + (lane & 15)) * kWgGP + (lane >> 4);
+    int boff[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        const int n = 16 * (nt0 + j) + (lane & 15);
+        const int i = n / kK, t = n - kK * i;
+        boff[j] = i * kWgTP + t + (lane >> 4);
+    }
+    mx4 acc[9];
+#pragma unroll
+    for (int j = 0; j < 9; ++j) acc[j] = mx4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;                             // bias: channel tid % 32, positions tid / 32 + 8 m
+    const float* ti = &tin[0][0];
+    const float* tg = &tgo[0][0];
+    constexpr unsigned kOut = 0x80000000u;
+    const int64_t items = (int64_t)rows * nseg;
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int r = (int)(it / nseg);
+        const int x0 = (int)(it - (int64_t)r * nseg) * kWgSeg;
+        __syncthreads();                                   // previous item no longer read
+        const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(in + (size_t)r * 32 * len), 0, (int)(32u * (unsigned)len * 4u), 0x00020000);
+        const __amdgpu_buffer_rsrc_t rgo = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(go + (size_t)r * 32 * len), 0, (int)(32u * (unsigned)len * 4u), 0x00020000);
+        for (int ci = wave; ci < 32; ci += 4) {
+            const unsigned rowoff = (unsigned)ci * (unsigned)len * 4u;
+            for (int g = 0; g * 64 < kWgSeg + 2 * kHalo; ++g) {
+                const int xx = g * 64 + lane;
+                const int x = x0 + xx - kHalo;
+                const unsigned vo = (x >= 0 && x < len) ? (unsigned)x * 4u : kOut;
+                if (xx < kWgSeg + 2 * kHalo)               // lanes past the row write nothing
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rin, lds_ptr(&tin[ci][g * 64]), 4, vo,
+                                                             rowoff, 0, 0);
+            }
+            for (int g = 0; g * 64 < kWgSeg; ++g) {
+                const int x = x0 + g * 64 + lane;
+                const unsigned vo = x < len ? (unsigned)x * 4u : kOut;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rgo, lds_ptr(&tgo[ci][g * 64]), 4, vo,
+                                                         rowoff, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int xx = tid >> 5; xx < kWgSeg; xx += 8) bsum += tgo[tid & 31][xx];
+#pragma unroll 4
+        for (int xs = 0; xs < kWgSeg; xs += 4) {
+            const float a = tg[aoff + xs];
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ti[boff[j] + xs], acc[j], 0, 0, 0);
+        }
+    }
+    // D: lane l, register q -> row o = 16 ot + 4 (l / 16) + q, column n = 16 nt + l % 16
+    float* pb = part + (size_t)blockIdx.x * kWgPart;
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int o = ot * 16 + 4 * (lane >> 4) + q;
+            pb[o * kWgN + 16 * (nt0 + j) + (lane & 15)] = acc[j][q];
+        }
+    __syncthreads();
+    float* red = &tgo[0][0];
+    red[tid] = bsum;
+    __syncthreads();
+    if (tid < 32) {
+        float sb = 0.f;
+#pragma unroll
+        for (int st = 0; st < 8; ++st) sb += red[st * 32 + tid];
+        pb[32 * kWgN + tid] = sb;
+    }
+}
+
+// gw[e] += sum_b part[b][e] (e < 32 x 288), gb[o] += sum_b part[b][32 x 288 + o]
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ part, int nblk,
+                                                         float* __restrict__ gw,
+                                                         float* __restrict__ gb)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kWgPart) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * kWgPart + e];
+    if (e < 32 * kWgN) gw[e] += s;
+    else if (gb) gb[e - 32 * kWgN] += s;
+}
+
+// Weight gradients of the layers with one input or one output channel
+// (32 -> 1 and 1 -> 32; both weight tensors are indexed c k + t with c the
+// 32-channel side): memory-bound like their forward passes.  Thread
+// (channel group, position stream) owns 4 of the 32 channels with their 9
+// taps and bias sums and walks positions 4 at a time across all rows,
+// reading the 12 samples of the input side and 4 of the gradient side with
+// 16-byte loads where the row allows.  Each block reduces its threads' sums
+// (wave shuffles, then LDS) into one partial; a second kernel adds the
+// partials in a fixed order.
+constexpr int kWsCG = 4;                          // channels per thread
+constexpr int kWsBlocks = 128;                    // position streams (blocks) per channel group
+constexpr int kWsVals = kWsCG * (kK + 1);         // sums per thread: 9 taps + bias per channel
+
+// gout[x0 .. x0 + 3] of one row, zero at or beyond len.
+__device__ __forceinline__ void load4(const float* __restrict__ row, int x0, int len, bool vec4,
+                                      float (&g)[4])
+{
+    if (vec4) {
+        const float4 a = *reinterpret_cast<const float4*>(row + x0);
+        g[0] = a.x; g[1] = a.y; g[2] = a.z; g[3] = a.w;
+    } else {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) g[p] = x0 + p < len ? row[x0 + p] : 0.f;
+    }
+}
+
+template <bool TO1>
+__global__ __launch_bounds__(256) void wgrad_small_kernel(const float* __restrict__ in,
+                                                          const float* __restrict__ go,
+                                                          float* __restrict__ part, int rows,
+                                                          int len, int nq)
+{
+    __shared__ float red[4][kWsVals];
+    const int cg = blockIdx.x / kWsBlocks, pbk = blockIdx.x - cg * kWsBlocks;
+    const int c0 = cg * kWsCG;
+    float acc[kWsCG][kK + 1];
+#pragma unroll
+    for (int c = 0; c < kWsCG; ++c)
+#pragma unroll
+        for (int t = 0; t <= kK; ++t) acc[c][t] = 0.f;
+    const bool al = aligned16(in, go, in, go) && (len & 3) == 0;
+    const int64_t items = (int64_t)rows * nq;
+    for (int64_t it = (int64_t)pbk * 256 + threadIdx.x; it < items; it += (int64_t)kWsBlocks * 256) {
+        const int r = (int)(it / nq);
+        const int x0 = 4 * (int)(it - (int64_t)r * nq);
+        const bool vec = al && x0 >= 4 && x0 + 8 <= len;
+        const bool vec4 = al && x0 + 4 <= len;
+        if (TO1) {
+            // gw[0][i][t] += sum gout[0][x] in[i][x + t - 4]
+            float g[4];
+            load4(go + (size_t)r * len, x0, len, vec4, g);
+#pragma unroll
+            for (int c = 0; c < kWsCG; ++c) {
+                float v[12];
+                load12(in + ((size_t)r * 32 + c0 + c) * len, x0, len, vec, v);
+#pragma unroll
+                for (int t = 0; t < kK; ++t)
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) acc[c][t] = fmaf(g[p], v[p + t], acc[c][t]);
+            }
+            acc[0][kK] += (g[0] + g[1]) + (g[2] + g[3]);
+        } else {
+            // gw[o][0][t] += sum gout[o][x] in[0][x + t - 4]
+            float v[12];
+            load12(in + (size_t)r * len, x0, len, vec, v);
+#pragma unroll
+            for (int c = 0; c < kWsCG; ++c) {
+                float g[4];
+                load4(go + ((size_t)r * 32 + c0 + c) * len, x0, len, vec4, g);
+#pragma unroll
+                for (int t = 0; t < kK; ++t)
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) acc[c][t] = fmaf(g[p], v[p + t], acc[c][t]);
+                acc[c][kK] += (g[0] + g[1]) + (g[2] + g[3]);
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < kWsCG; ++c)
+#pragma unroll
+        for (int t = 0; t <= kK; ++t) {
+            float x = acc[c][t];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+            if (lane == 0) red[wave][c * (kK + 1) + t] = x;
+        }
+    __syncthreads();
+    if (threadIdx.x < kWsVals) {
+        const int q = threadIdx.x;
+        part[(size_t)blockIdx.x * kWsVals + q] = (red[0][q] + red[1][q]) + (red[2][q] + red[3][q]);
+    }
+}
+
+// gw[c k + t] += sum over streams; bias: gb[c] (1 -> 32) or gb[0] (32 -> 1)
+template <bool TO1>
+__global__ __launch_bounds__(256) void wgrad_small_reduce_kernel(const float* __restrict__ part,
+                                                                 float* __restrict__ gw,
+                                                                 float* __restrict__ gb)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;    // (channel group, value)
+    if (e >= 8 * kWsVals) return;
+    const int cg = e / kWsVals, q = e - cg * kWsVals;
+    const int c = cg * kWsCG + q / (kK + 1), t = q % (kK + 1);
+    float s = 0.f;
+    for (int b = 0; b < kWsBlocks; ++b) s += part[((size_t)cg * kWsBlocks + b) * kWsVals + q];
+    if (t < kK) gw[c * kK + t] += s;
+    else if (gb && (!TO1 || c == 0)) gb[TO1 ? 0 : c] += s;
+}
+
 // loss[0] += sum (a - b)^2 ;  grad = scale (a - b)  (scale = 2/n: gradient of the mean)
 __global__ __launch_bounds__(256) void sqerr_kernel(const float* __restrict__ a,
                                                     const float* __restrict__ b,
@@ -664,15 +888,59 @@ fdk_status launch_conv1d_backward_data(int cin, int cout, int rows, int len, con
     return conv<1, 1, true>(rows, len, gout, w, nullptr, mask, nullptr, 1.f, 0, gin, st);
 }
 
+template <bool TO1>
+fdk_status wgrad_small(int rows, int len, const float* in, const float* gout, float* gw,
+                       float* gb, hipStream_t st)
+{
+    const int nq = (len + 3) / 4;
+    constexpr int nblk = 8 * kWsBlocks;
+    void* part = nullptr;
+    fdk_status s = device_alloc_async((size_t)nblk * kWsVals * sizeof(float), st, &part);
+    if (s != FDK_OK) return s;
+    hipLaunchKernelGGL(wgrad_small_kernel<TO1>, dim3(nblk), dim3(256), 0, st, in, gout,
+                       (float*)part, rows, len, nq);
+    s = check_launch("conv1d weight-gradient kernel");
+    if (s == FDK_OK) {
+        hipLaunchKernelGGL(wgrad_small_reduce_kernel<TO1>, dim3((8 * kWsVals + 255) / 256), dim3(256),
+                           0, st, (const float*)part, gw, gb);
+        s = check_launch("weight-gradient reduction kernel");
+    }
+    const fdk_status s2 = device_free_async(part, st);
+    return s != FDK_OK ? s : s2;
+}
+
+fdk_status wgrad32(int rows, int len, const float* in, const float* gout, float* gw, float* gb,
+                   hipStream_t st)
+{
+    const int nseg = (len + kWgSeg - 1) / kWgSeg;
+    const int64_t items = (int64_t)rows * nseg;
+    if ((int64_t)len * 32 * 4 >= (1ll << 31))
+        return fail(FDK_E_UNSUPPORTED, "conv1d rows too long for one launch");
+    const int nblk = (int)(items < kWgBlocks ? items : kWgBlocks);
+    void* part = nullptr;
+    fdk_status s = device_alloc_async((size_t)nblk * kWgPart * sizeof(float), st, &part);
+    if (s != FDK_OK) return s;
+    hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3((unsigned)nblk), dim3(256), 0, st, in, gout,
+                       (float*)part, rows, len, nseg);
+    s = check_launch("conv1d weight-gradient kernel");
+    if (s == FDK_OK) {
+        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgPart + 255) / 256), dim3(256), 0, st,
+                           (const float*)part, nblk, gw, gb);
+        s = check_launch("weight-gradient reduction kernel");
+    }
+    const fdk_status s2 = device_free_async(part, st);
+    return s != FDK_OK ? s : s2;
+}
+
 fdk_status launch_conv1d_backward_weight(int cin, int cout, int rows, int len, const float* in,
                                          const float* gout, float* gw, float* gb, void* stream)
 {
     hipStream_t st = (hipStream_t)stream;
     if (!supported(cin, cout))
         return fail(FDK_E_UNSUPPORTED, "conv1d channels must be 1 or 32");
-    if (cin == 1 && cout == 32) return wgrad<1, 32>(rows, len, in, gout, gw, gb, st);
-    if (cin == 32 && cout == 32) return wgrad<32, 32>(rows, len, in, gout, gw, gb, st);
-    if (cin == 32 && cout == 1) return wgrad<32, 1>(rows, len, in, gout, gw, gb, st);
+    if (cin == 1 && cout == 32) return wgrad_small<false>(rows, len, in, gout, gw, gb, st);
+    if (cin == 32 && cout == 32) return wgrad32(rows, len, in, gout, gw, gb, st);
+    if (cin == 32 && cout == 1) return wgrad_small<true>(rows, len, in, gout, gw, gb, st);
     return wgrad<1, 1>(rows, len, in, gout, gw, gb, st);
 }
 

@@ -89,7 +89,7 @@ def test_conv_backward_data_parity(cin, cout, n):
 
 
 @pytest.mark.parametrize("cin,cout", PAIRS)
-@pytest.mark.parametrize("rows,n", [(1, 5), (37, 129), (2100, 64)])
+@pytest.mark.parametrize("rows,n", [(1, 5), (37, 129), (2100, 64), (600, 512)])
 def test_conv_backward_weight_parity(cin, cout, rows, n):
     seed = 700 + 100 * cin + cout + rows + n
     x = wl.gaussian(seed, (rows, cin, n))
@@ -101,6 +101,22 @@ def test_conv_backward_weight_parity(cin, cout, rows, n):
     rw, rb = ol.conv_backward_weight(x.astype(np.float64), g.astype(np.float64))
     assert rel(host(gw), rw + gw0) <= TOL32
     assert rel(host(gb), rb + gb0) <= TOL32
+
+
+@pytest.mark.parametrize("cin,cout", [(32, 32), (32, 1), (1, 32)])
+def test_conv_backward_weight_deterministic(cin, cout):
+    """The weight gradients of the 32-channel layers are summed per block and
+    then across blocks in a fixed order: two calls agree bitwise."""
+    rows, n = 300, 512
+    x = dev(wl.gaussian(950 + cin, (rows, cin, n)))
+    g = dev(wl.gaussian(951 + cout, (rows, cout, n)))
+    out = []
+    for _ in range(2):
+        gw = torch.zeros((cout, cin, 9), dtype=torch.float32, device="cuda")
+        gb = torch.zeros((cout,), dtype=torch.float32, device="cuda")
+        L.conv1d_backward_weight(x, g, gw, gb)
+        out.append((host(gw), host(gb)))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
 def test_cosine_weight_parity():

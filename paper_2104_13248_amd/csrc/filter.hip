@@ -9,9 +9,17 @@
 // with the Ram-Lak kernel h[0] = 1/(4 tau^2), h[odd n] = -1/(pi^2 n^2 tau^2),
 // h[even n != 0] = 0 and tau = du sod / sdd.
 //
-// One block per detector row: the weighted row and the odd-tap coefficients
-// live in LDS; each thread produces several outputs, reading each q once per
-// pair of symmetric taps (h is even).
+// Rows up to 2048 pixels are filtered through the Fourier domain: h is even,
+// so its length-M transform H (M the power of two >= 2 nw - 1, which keeps the
+// circular convolution free of wrap-around over the nw outputs) is real, and
+// two weighted rows a, b packed as z = a + i b give z * h = (a * h) + i (b * h)
+// from one forward transform, a multiplication by H and one inverse transform.
+// A block owns such a pair of rows; the transforms are Stockham radix-8/4/2
+// passes in LDS (natural order in and out), the inverse taken as
+// conj(FFT(conj(.))) with 1/M and the FDK constants folded into H.  H and the
+// twiddle factors are built per call in FP64.  Longer rows use a direct
+// convolution: one block per row, the weighted row and the odd-tap
+// coefficients in LDS, each q read once per pair of symmetric taps.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,6 +30,7 @@ namespace fdk {
 namespace {
 
 constexpr int kFilterThreads = 256;
+constexpr int kFftMaxRow = 2048;   // rows up to this length are filtered through the Fourier domain
 
 struct FilterArgs {
     const float* raw;
@@ -66,6 +75,161 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const FilterArgs
         }
         dst[c] = fmaf(A.h0, q[c], acc);
     }
+}
+
+// ---- Fourier-domain filter
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place forward DFT of R = 2, 4 or 8 points (kernel e^{-2 pi i n k / R}).
+template <int R>
+__device__ __forceinline__ void dft(float2 (&v)[R])
+{
+    if constexpr (R == 2) {
+        const float2 a = v[0], b = v[1];
+        v[0] = make_float2(a.x + b.x, a.y + b.y);
+        v[1] = make_float2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        const float2 t0 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const float2 t1 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const float2 t2 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const float2 t3 = make_float2(v[1].y - v[3].y, v[3].x - v[1].x);   // -i (v1 - v3)
+        v[0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+        v[2] = make_float2(t0.x - t2.x, t0.y - t2.y);
+        v[1] = make_float2(t1.x + t3.x, t1.y + t3.y);
+        v[3] = make_float2(t1.x - t3.x, t1.y - t3.y);
+    } else {
+        // X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k]
+        float2 e[4] = {v[0], v[2], v[4], v[6]};
+        float2 o[4] = {v[1], v[3], v[5], v[7]};
+        dft<4>(e);
+        dft<4>(o);
+        constexpr float h = 0.70710678118654752f;
+        o[1] = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));     // * (h, -h)
+        o[2] = make_float2(o[2].y, -o[2].x);                                   // * -i
+        o[3] = make_float2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));    // * (-h, -h)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = make_float2(e[k].x + o[k].x, e[k].y + o[k].y);
+            v[k + 4] = make_float2(e[k].x - o[k].x, e[k].y - o[k].y);
+        }
+    }
+}
+
+// LDS index of element e: one pad word pair per 32 elements breaks the
+// power-of-two strides of the passes' writes across the banks.
+__device__ __forceinline__ int fpad(int e) { return e + (e >> 5); }
+
+// One Stockham pass of radix R after sub-transforms of length NS: butterfly j
+// reads elements j + r M/R, twiddles them by W_{NS R}^{(j mod NS) r}, and
+// writes (j / NS) NS R + (j mod NS) + r NS.
+template <int M, int R, int NS>
+__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid)
+{
+    constexpr int B = M / R;
+    constexpr int J = (B + kFilterThreads - 1) / kFilterThreads;
+    float2 v[J][R];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = tid + kFilterThreads * q;
+        if (j < B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[fpad(j + r * B)];
+            if constexpr (NS > 1) {
+                const int k = j % NS;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[k * r * (M / (NS * R))]);
+            }
+            dft<R>(v[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = tid + kFilterThreads * q;
+        if (j < B) {
+            const int d = (j / NS) * NS * R + j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[fpad(d + r * NS)] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Forward length-M DFT of buf (natural order in and out).
+template <int M, int NS = 1>
+__device__ __forceinline__ void fft(float2* buf, const float2* __restrict__ tw, int tid)
+{
+    if constexpr (NS < M) {
+        constexpr int R = M / NS >= 8 ? 8 : M / NS;
+        stockham_pass<M, R, NS>(buf, tw, tid);
+        fft<M, NS * R>(buf, tw, tid);
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const FilterArgs A,
+                                                                    const float* __restrict__ H,
+                                                                    const float2* __restrict__ tw,
+                                                                    int64_t nrows)
+{
+    __shared__ float2 buf[M + M / 32];
+    const int tid = threadIdx.x;
+    const int64_t row0 = 2 * (int64_t)blockIdx.x;
+    const bool two = row0 + 1 < nrows;
+    const float* s0 = A.raw + row0 * A.nw;
+    const float* s1 = s0 + A.nw;
+    const float v0 = ((float)(int)(row0 % A.nh) - A.cv) * A.dv;
+    const float v1 = ((float)(int)((row0 + 1) % A.nh) - A.cv) * A.dv;
+    const float w0 = A.sdd2 + v0 * v0, w1 = A.sdd2 + v1 * v1;
+    for (int c = tid; c < M; c += kFilterThreads) {
+        float a = 0.f, b = 0.f;
+        if (c < A.nw) {
+            const float umm = ((float)c - A.cu) * A.du;
+            a = s0[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w0)));
+            if (two) b = s1[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w1)));
+        }
+        buf[fpad(c)] = make_float2(a, b);
+    }
+    __syncthreads();
+    fft<M>(buf, tw, tid);
+    // conj(Z H): H is real
+    for (int k = tid; k < M; k += kFilterThreads) {
+        const float2 z = buf[fpad(k)];
+        const float h = H[k];
+        buf[fpad(k)] = make_float2(z.x * h, -z.y * h);
+    }
+    __syncthreads();
+    fft<M>(buf, tw, tid);
+    // z * h = conj(FFT(conj(Z H))) / M (1/M is in H): row a = Re, row b = -Im
+    float* d0 = A.out + row0 * A.nw;
+    for (int c = tid; c < A.nw; c += kFilterThreads) {
+        const float2 y = buf[fpad(c)];
+        d0[c] = y.x;
+        if (two) d0[A.nw + c] = -y.y;
+    }
+}
+
+// tw[e] = exp(-2 pi i e / M); H[k] = (1/M) (h0 + 2 sum_{odd n < nw} hs / n^2
+// cos(2 pi k n / M)), the transform of the wrapped, even kernel; FP64.
+__global__ __launch_bounds__(256) void filter_tables_kernel(int M, int nw, double h0, double hs,
+                                                           float2* __restrict__ tw,
+                                                           float* __restrict__ H)
+{
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= M) return;
+    double sn, cs;
+    sincospi(2.0 * (double)e / (double)M, &sn, &cs);
+    tw[e] = make_float2((float)cs, (float)-sn);
+    double acc = h0;
+    for (int n = 1; n < nw; n += 2) {
+        const int idx = (int)(((int64_t)e * n) % M);
+        acc += 2.0 * hs / ((double)n * (double)n) * cospi(2.0 * (double)idx / (double)M);
+    }
+    H[e] = (float)(acc / (double)M);
 }
 
 // Step 1 alone (the input of the learned row filter): q = raw * cosine weight.
@@ -120,6 +284,36 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
 {
     const FilterArgs A = filter_args(a);
     const int64_t rows = (int64_t)a.np * a.nh;
+    hipStream_t st = (hipStream_t)stream;
+    if (a.nw <= kFftMaxRow) {
+        int M = 16;
+        while (M < 2 * a.nw - 1) M *= 2;
+        if ((rows + 1) / 2 >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "too many detector rows");
+        void* tab = nullptr;
+        fdk_status s = device_alloc_async((size_t)M * (sizeof(float) + sizeof(float2)), st, &tab);
+        if (s != FDK_OK) return s;
+        float2* tw = (float2*)tab;
+        float* H = (float*)(tw + M);
+        const double tau = a.du * a.sod / a.sdd;
+        const double wang = a.arc / (2.0 * (double)a.np_total);
+        const double pi = 3.14159265358979323846;
+        hipLaunchKernelGGL(filter_tables_kernel, dim3((M + 255) / 256), dim3(256), 0, st, M, a.nw,
+                           1.0 / (4.0 * tau * tau) * tau * wang, -1.0 / (pi * pi * tau * tau) * tau * wang,
+                           tw, H);
+        s = check_launch("filter table kernel");
+        if (s == FDK_OK) {
+            const dim3 g((unsigned)((rows + 1) / 2)), b(kFilterThreads);
+            switch (M) {
+#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, b, 0, st, A, (const float*)H, (const float2*)tw, rows); break;
+                FDK_FFT(16) FDK_FFT(32) FDK_FFT(64) FDK_FFT(128) FDK_FFT(256) FDK_FFT(512)
+                FDK_FFT(1024) FDK_FFT(2048) FDK_FFT(4096)
+#undef FDK_FFT
+            }
+            s = check_launch("filter kernel");
+        }
+        const fdk_status s2 = device_free_async(tab, st);
+        return s != FDK_OK ? s : s2;
+    }
     if (rows >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "too many detector rows");
     const size_t lds = (size_t)(a.nw + (a.nw + 1) / 2 + 1) * sizeof(float);
     if (lds > 64 * 1024) {
@@ -127,8 +321,7 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
                                 (int)lds) != hipSuccess)
             return fail(FDK_E_DEVICE, "cannot raise the LDS limit of the filter kernel");
     }
-    hipLaunchKernelGGL(filter_kernel, dim3((unsigned)rows), dim3(kFilterThreads), lds,
-                       (hipStream_t)stream, A);
+    hipLaunchKernelGGL(filter_kernel, dim3((unsigned)rows), dim3(kFilterThreads), lds, st, A);
     return check_launch("filter kernel");
 }
 

@@ -114,6 +114,186 @@ def cpu_baseline(cfg, mats, seconds: float):
                       "Gaussian projections of the same shape; %.1f s" % (b2, nx, ny, nz, npv, dt)}
 
 
+# Dense FP32 matrix-core peak of MI355X (v_mfma_f32_* instructions).
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def _timed_ms(fn, reps=5):
+    """Average ms of fn() over reps runs, HIP events on torch's current
+    stream (every operation below runs on that stream)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def ops_report(seconds: float) -> int:
+    """--ops: one JSON line per operation beside the back-projector (forward
+    projector, FDK filter, learned-filter layers), each against its roofline,
+    with the FP64 oracle timed on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+    import oracle
+    from oracle import learned as ol
+    import workloads as wl
+    import paper_2104_13248_amd as fdk
+    from paper_2104_13248_amd import learned as L
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    threads = oracle.max_threads()
+    budget = seconds / 4.0                 # oracle seconds per operation, about
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    def scaled(run, b0, cap, cost):
+        """Grow the sample size b until the oracle takes ~budget seconds."""
+        b = b0
+        dt = run(b)
+        while dt < 0.1 and 2 * b <= cap:
+            b *= 2
+            dt = run(b)
+        b2 = int(max(b0, min(cap, b * (budget / max(dt, 1e-6)) ** (1.0 / cost))))
+        return b2, run(b2)
+
+    # ---- forward projector (exact transpose), 256^3 x 360 views x 384^2
+    cfg = wl.CONFIGS["c4"]
+    nz, ny, nx = cfg["shape"]
+    npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
+    mats = np.asarray(fdk.scan_matrices(cfg["scan"], npv, nh, nw))
+    vol_h = wl.gaussian(cfg["seed"] + 7, cfg["shape"])
+    vol = torch.from_numpy(vol_h.astype(np.float32)).to(dev)
+    proj = torch.zeros((npv, nh, nw), dtype=torch.float32, device=dev)
+    ms = _timed_ms(lambda: fdk.forwardproject(vol, proj, mats, cfg["voxel"]))
+    upd = nx * ny * nz * npv
+    gups = upd / (ms * 1e-3) / 1e9
+    log("ops: forward projection %.2f ms" % ms)
+
+    def fp_run(b):
+        c = nx // 2 - b // 2
+        sub = np.ascontiguousarray(vol_h[c:c + b, c:c + b, c:c + b], dtype=np.float64)
+        t = time.perf_counter()
+        oracle.forwardproject(sub, mats, nh, nw, cfg["voxel"])
+        return time.perf_counter() - t
+
+    b, dt = scaled(fp_run, 16, nx, 3.0)
+    emit({"op": "forward_projection", "metric": "GUPS (voxel-view updates/s)", "value": gups,
+          "unit": "GUPS", "ms": ms, "dtype": "f32", "data": "synthetic: seeded Gaussian volume",
+          "config": {"workload": "fdk_forwardprojection_256x256x256_360views_384x384",
+                     "voxel_mm": list(cfg["voxel"]), "views": npv, "detector": [nh, nw]},
+          "roofline": {"bound": "alu", "achieved": OPS_PER_UPDATE * gups / 1e3,
+                       "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": OPS_PER_UPDATE * gups / 1e3 / VALU_PEAK_TOPS,
+                       "ops_per_update": OPS_PER_UPDATE},
+          "cpu_baseline": {"value": b ** 3 * npv / dt / 1e9, "unit": "GUPS", "cores": threads,
+                           "kind": "oracle",
+                           "sample": "centred %d^3 sub-block, all %d views; %.1f s" % (b, npv, dt)}})
+    del vol, proj
+
+    # ---- FDK filter, 128 views x 1024^2 (one chunk of the 1024-view stack)
+    cfg = wl.CONFIGS["c2"]
+    nh, nw = cfg["nh"], cfg["nw"]
+    views = 128
+    raw_h = wl.gaussian(cfg["seed"] + 11, (views, nh, nw))
+    raw = torch.from_numpy(raw_h).to(dev)
+    out = torch.empty_like(raw)
+    ms = _timed_ms(lambda: fdk.fdk_filter(raw, cfg["scan"], np_total=cfg["np"], out=out))
+    nbytes = 8 * raw.numel()               # read and write one float32 per pixel
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log("ops: filter %.2f ms" % ms)
+
+    def filt_run(v):
+        t = time.perf_counter()
+        oracle.fdk_filter(raw_h[:v].astype(np.float64), cfg["scan"], np_total=cfg["np"])
+        return time.perf_counter() - t
+
+    nv, dt = scaled(filt_run, 1, views, 1.0)
+    emit({"op": "fdk_filter", "metric": "FDK filter throughput (HBM bytes/s of the stack)",
+          "value": gbs, "unit": "GB/s", "ms": ms, "dtype": "f32",
+          "data": "synthetic: seeded Gaussian line integrals",
+          "config": {"workload": "fdk_filter_128views_1024x1024", "algorithmic_bytes": nbytes},
+          "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbs / HBM_PEAK_GBS},
+          "cpu_baseline": {"value": 8.0 * nv * nh * nw / dt / 1e9, "unit": "GB/s",
+                           "cores": threads, "kind": "oracle",
+                           "sample": "%d views of %dx%d; %.1f s" % (nv, nh, nw, dt)}})
+    del raw, out
+
+    # ---- learned-filter layers, 46080 rows x 512 (one 90-view scan, 512^2)
+    rows, n = 90 * 512, 512
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    x32 = torch.randn((rows, 32, n), generator=g, device=dev)
+    w2 = torch.randn((32, 32, 9), generator=g, device=dev) * 0.1
+    w3 = torch.randn((1, 32, 9), generator=g, device=dev) * 0.1
+    b2 = torch.zeros(32, device=dev)
+    y32 = torch.empty_like(x32)
+    y1 = torch.empty((rows, 1, n), device=dev)
+    gw = torch.zeros_like(w2)
+    gb = torch.zeros_like(b2)
+    flops = 2.0 * rows * n * 32 * 32 * 9
+    xs = np.random.default_rng(5).standard_normal((64, 32, n))
+    ws = np.random.default_rng(6).standard_normal((32, 32, 9)) * 0.1
+
+    def conv_run(r):
+        t = time.perf_counter()
+        ol.conv(xs[:r], ws)
+        return time.perf_counter() - t
+
+    def wgrad_run(r):
+        t = time.perf_counter()
+        ol.conv_backward_weight(xs[:r], xs[:r])
+        return time.perf_counter() - t
+
+    for name, fn, run, what in (("learned_conv32_forward",
+                                 lambda: L.conv1d_forward(x32, w2, b2, relu=True, out=y32),
+                                 conv_run, "forward"),
+                                ("learned_conv32_weight_gradient",
+                                 lambda: L.conv1d_backward_weight(x32, x32, gw, gb),
+                                 wgrad_run, "weight gradient")):
+        r_cpu, dt_cpu = scaled(run, 1, 64, 1.0)
+        cpu_tflops = 2.0 * r_cpu * n * 32 * 32 * 9 / dt_cpu / 1e12
+        ms = _timed_ms(fn)
+        tf = flops / (ms * 1e-3) / 1e12
+        log("ops: %s %.2f ms" % (name, ms))
+        emit({"op": name, "metric": "FP32 TFLOP/s (32 -> 32 channels, 9 taps)", "value": tf,
+              "unit": "TFLOP/s", "ms": ms, "dtype": "f32", "data": "synthetic: seeded Gaussian",
+              "config": {"workload": "conv1d_32x32_k9_46080rows_x512", "flops": flops},
+              "roofline": {"bound": "mfma", "achieved": tf, "peak": MFMA_F32_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": tf / MFMA_F32_PEAK_TFLOPS},
+              "cpu_baseline": {"value": cpu_tflops, "unit": "TFLOP/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": "%s of %d rows (FP64 NumPy); %.1f s" % (what, r_cpu, dt_cpu)}})
+    ms = _timed_ms(lambda: L.conv1d_forward(x32, w3, None, out=y1))
+    nbytes = 4.0 * rows * n * 33
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log("ops: conv 32->1 %.2f ms" % ms)
+    w3s = np.random.default_rng(7).standard_normal((1, 32, 9)) * 0.1
+
+    def to1_run(r):
+        t = time.perf_counter()
+        ol.conv(xs[:r], w3s)
+        return time.perf_counter() - t
+
+    r1, dt1 = scaled(to1_run, 1, 64, 1.0)
+    emit({"op": "learned_conv_32to1_forward", "metric": "HBM bytes/s (32 channels in, 1 out)",
+          "value": gbs, "unit": "GB/s", "ms": ms, "dtype": "f32", "data": "synthetic: seeded Gaussian",
+          "config": {"workload": "conv1d_32x1_k9_46080rows_x512", "algorithmic_bytes": nbytes},
+          "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbs / HBM_PEAK_GBS},
+          "cpu_baseline": {"value": 4.0 * r1 * n * 33 / dt1 / 1e9, "unit": "GB/s",
+                           "cores": threads, "kind": "oracle",
+                           "sample": "%d rows (FP64 NumPy); %.1f s" % (r1, dt1)}})
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,12 +304,17 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy (reference for byte counters)")
+    ap.add_argument("--ops", action="store_true",
+                    help="report the operations beside the back-projector instead (one JSON "
+                         "line each: forward projector, FDK filter, learned-filter layers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the back-projector has no multi-GPU path in this "
               "build (a z-slab split needs no exchange; see the design notes). Use --gpus 1.",
               file=sys.stderr)
         return 2
+    if args.ops:
+        return ops_report(args.cpu_seconds)
 
     import numpy as np
     import torch

@@ -214,22 +214,26 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const Filter
 }
 
 // tw[e] = exp(-2 pi i e / M); H[k] = (1/M) (h0 + 2 sum_{odd n < nw} hs / n^2
-// cos(2 pi k n / M)), the transform of the wrapped, even kernel; FP64.
-__global__ __launch_bounds__(256) void filter_tables_kernel(int M, int nw, double h0, double hs,
-                                                           float2* __restrict__ tw,
-                                                           float* __restrict__ H)
+// cos(2 pi k n / M)), the transform of the wrapped, even kernel; FP64.  One
+// wave per k: lanes split the sum over n, then a shuffle reduction.
+__global__ __launch_bounds__(64) void filter_tables_kernel(int M, int nw, double h0, double hs,
+                                                          float2* __restrict__ tw,
+                                                          float* __restrict__ H)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= M) return;
-    double sn, cs;
-    sincospi(2.0 * (double)e / (double)M, &sn, &cs);
-    tw[e] = make_float2((float)cs, (float)-sn);
-    double acc = h0;
-    for (int n = 1; n < nw; n += 2) {
-        const int idx = (int)(((int64_t)e * n) % M);
-        acc += 2.0 * hs / ((double)n * (double)n) * cospi(2.0 * (double)idx / (double)M);
+    const int k = blockIdx.x, lane = threadIdx.x;
+    double acc = 0.0;
+    for (int n = 2 * lane + 1; n < nw; n += 128) {
+        const int idx = (int)(((int64_t)k * n) % M);
+        acc += hs / ((double)n * (double)n) * cospi(2.0 * (double)idx / (double)M);
     }
-    H[e] = (float)(acc / (double)M);
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m, 64);
+    if (lane == 0) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)M, &sn, &cs);
+        tw[k] = make_float2((float)cs, (float)-sn);
+        H[k] = (float)((h0 + 2.0 * acc) / (double)M);
+    }
 }
 
 // Step 1 alone (the input of the learned row filter): q = raw * cosine weight.
@@ -297,7 +301,7 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
         const double tau = a.du * a.sod / a.sdd;
         const double wang = a.arc / (2.0 * (double)a.np_total);
         const double pi = 3.14159265358979323846;
-        hipLaunchKernelGGL(filter_tables_kernel, dim3((M + 255) / 256), dim3(256), 0, st, M, a.nw,
+        hipLaunchKernelGGL(filter_tables_kernel, dim3(M), dim3(64), 0, st, M, a.nw,
                            1.0 / (4.0 * tau * tau) * tau * wang, -1.0 / (pi * pi * tau * tau) * tau * wang,
                            tw, H);
         s = check_launch("filter table kernel");

@@ -156,7 +156,7 @@ def test_filter_parity():
     assert e <= TOL32
 
 
-@pytest.mark.parametrize("nw", [1, 2, 7, 300, 1027])
+@pytest.mark.parametrize("nw", [1, 2, 7, 300, 1027, 2048, 2049])
 def test_filter_ragged_rows(nw):
     scan = dict(sod=600.0, sdd=1100.0, du=0.8, dv=1.2, arc=2 * math.pi, theta0=0.0,
                 u_off=1.5, v_off=-0.5)

@@ -40,6 +40,8 @@ FP_CASES = [
     ("c1", (64, 64, 64), (64, 128, 128), {}, (0.0, 0.0, 0.0)),
     ("c1", (9, 21, 17), (37, 50, 70), dict(theta0=0.4, u_off=2.5, v_off=-1.0), (1.0, -2.0, 3.0)),
     ("c1", (96, 48, 48), (24, 400, 300), dict(sod=120.0, sdd=400.0), (0.0, 0.0, 0.0)),
+    # odd detector width: a full 256-column chunk and a ragged one of 45
+    ("c1", (20, 18, 22), (16, 40, 301), dict(theta0=0.7, u_off=-1.5), (0.5, 0.0, -1.0)),
 ]
 
 

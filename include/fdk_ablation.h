@@ -19,6 +19,16 @@
  *                            Section 3.1.2 removed), taps from global memory,
  *                            the volume read and written once per batch of nb
  *                            views.
+ *   FDK_VARIANT_SYMMETRY     production structure plus the geometric symmetry
+ *                            of Section 3.1.2: a thread owns slices k of the
+ *                            lower half and their mirrors nz-1-k, whose v is
+ *                            nh-1-v(k); the mirrored window is staged in
+ *                            descending row order so both updates share v, its
+ *                            row, fraction and LDS address.  Needs v(nz-1-k) =
+ *                            nh-1-v(k) in every view (a circular orbit with the
+ *                            detector's centre row on the orbit plane and the
+ *                            volume centred on it), else FDK_E_GEOMETRY; whole
+ *                            volume only; nb is ignored.
  *
  * nb: views per batch, 1 <= nb (values above np mean np).  proj: device
  * float32 [np][nh][nw] (sg->dtype must be FDK_F32, else FDK_E_UNSUPPORTED);
@@ -38,7 +48,8 @@ extern "C" {
 typedef enum {
     FDK_VARIANT_PRODUCTION = 0,
     FDK_VARIANT_GLOBAL_TAPS = 1,
-    FDK_VARIANT_LISTING1 = 2
+    FDK_VARIANT_LISTING1 = 2,
+    FDK_VARIANT_SYMMETRY = 3
 } fdk_bp_variant;
 
 fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const fdk_volume* vg, float* vol,

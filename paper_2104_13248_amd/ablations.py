@@ -28,7 +28,7 @@ import torch
 from . import backproject, scan_matrices
 from ._lib import FDK_F32, check, host_f64, lib, ptr, stack_struct, volume_struct
 
-VARIANTS = {"production": 0, "global_taps": 1, "listing1": 2}
+VARIANTS = {"production": 0, "global_taps": 1, "listing1": 2, "symmetry": 3}
 
 
 def backproject_variant(vol: torch.Tensor, proj: torch.Tensor, mats, voxel, variant: str,
@@ -89,6 +89,8 @@ def sweep(config: str = "c2", views: int | None = None, nbs=(1, 2, 4, 8, 16, 32,
         print(json.dumps(r), file=out, flush=True)
 
     emit("production", npv, _time(lambda: backproject(vol, proj, mats, cfg["voxel"]), reps))
+    emit("symmetry", npv, _time(lambda: backproject_variant(vol, proj, mats, cfg["voxel"],
+                                                            "symmetry"), reps))
     emit("global_taps", npv, _time(lambda: backproject_variant(vol, proj, mats, cfg["voxel"],
                                                                "global_taps"), reps))
     for nb in nbs:

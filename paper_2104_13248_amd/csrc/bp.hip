@@ -89,7 +89,8 @@ struct TileRow {
 };
 
 // Stage rows [r0, r0+R) x columns [c0, c0+C) of one view into the LDS tile,
-// zero outside the detector.  One buffer descriptor covers the view; an
+// zero outside the detector (REV: rows r0, r0 - 1, .., r0 - R + 1, tile row rr
+// holding detector row r0 - rr).  One buffer descriptor covers the view; an
 // out-of-range offset reads as zero.  The tile has `ralloc` rows of
 // TileRow::W words (float32), or two such regions (binary16: even-offset
 // pairs, then odd-offset pairs).
@@ -99,7 +100,7 @@ struct TileRow {
 // instruction stages 64 / (W / 4) rows and the lanes of a row land side by
 // side.  Other windows are staged by 4-byte loads: lanes along a row, wave w
 // taking rows w, w + 4, ...
-template <int PITCH, bool F16>
+template <int PITCH, bool F16, bool REV = false>
 __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdgpu_buffer_rsrc_t& rs,
                                            int nh, unsigned row_bytes, int nw, int r0, int c0, int R,
                                            int C, int wave, int lane)
@@ -120,7 +121,7 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
             for (int rr0 = wave * RPI; rr0 < R; rr0 += kWaves * RPI) {
                 const int rr = rr0 + rsub;
                 if (rsub < RPI && rr < R) {
-                    const int r = r0 + rr;
+                    const int r = REV ? r0 - rr : r0 + rr;
                     const unsigned vo = (unsigned)r < (unsigned)nh ? (unsigned)r * row_bytes + colb : kOut;
                     lds_void* d = (lds_void*)(size_t)lds_addr(tile + rr0 * RW);
                     __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, vo, 0, 0, 0);
@@ -141,7 +142,7 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
             const unsigned voff = (unsigned)c < (unsigned)nw ? (unsigned)c * 4u : kOut;
             const bool keep = cc < C;
             for (int rr = wave; rr < R; rr += kWaves) {
-                const int r = r0 + rr;
+                const int r = REV ? r0 - rr : r0 + rr;
                 if ((unsigned)r < (unsigned)nh) {
                     if (keep) {
                         lds_void* dst = (lds_void*)(size_t)lds_addr(tile + rr * PITCH + g * 64);
@@ -172,7 +173,7 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
             const unsigned voo = (unsigned)po < (unsigned)nw ? (unsigned)po * 2u : kOut;
             const bool keep = mm < NE;
             for (int rr = wave; rr < R; rr += kWaves) {
-                const int r = r0 + rr;
+                const int r = REV ? r0 - rr : r0 + rr;
                 if ((unsigned)r < (unsigned)nh) {
                     if (keep) {
                         lds_void* de = (lds_void*)(size_t)lds_addr(tile + rr * HP + g * 64);
@@ -196,7 +197,7 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
         if (fix_left || fix_right) {
             __builtin_amdgcn_s_waitcnt(0);                    // this wave's row loads landed
             for (int rr = wave; rr < R; rr += kWaves) {
-                const int r = r0 + rr;
+                const int r = REV ? r0 - rr : r0 + rr;
                 if ((unsigned)r >= (unsigned)nh) continue;
                 if (fix_left && lane == 0) {
                     const unsigned p0 = __builtin_amdgcn_raw_buffer_load_b16(rs, 0u, (unsigned)r * row_bytes, 0);
@@ -254,6 +255,178 @@ __device__ __forceinline__ void update_half(float (&acc)[KZ], int k0, unsigned b
                 h1 = fmaf(fu, p11 - p10, p10);
             }
             acc[k0 + g0 + q] = fmaf(W, fmaf(fv[q], h1 - h0, h0), acc[k0 + g0 + q]);
+        }
+    }
+}
+
+// Symmetric variant (Section 3.1.2): KZ/2 direct slices kk = t and their
+// mirrors kk = KZ/2 + t.  The mirrored window is staged in descending row
+// order `moff` bytes after the direct one, so a mirrored update reads the same
+// window-relative rows with the same weights: v, its row and fraction, and the
+// LDS address are computed once for both updates.
+template <int KZ, int PITCH, bool F16>
+__device__ __forceinline__ void update_pair(float (&acc)[KZ], unsigned base, unsigned moff, float v0,
+                                            float dv, float fu, float W)
+{
+    constexpr int H = KZ / 2;
+    constexpr int kPrefetch = H < 4 ? H : 4;
+    constexpr int RW = TileRow<PITCH, F16>::W;
+#pragma unroll
+    for (int g0 = 0; g0 < H; g0 += kPrefetch) {
+        float fv[kPrefetch];
+        unsigned t[kPrefetch][4], tm[kPrefetch][4];
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            const float v = fmaf((float)(g0 + q), dv, v0);
+            fv[q] = __builtin_amdgcn_fractf(v);
+            const unsigned addr = __umul24((unsigned)(int)v, 4u * RW) + base;
+            const lds_u32* p = (const lds_u32*)(size_t)addr;
+            const lds_u32* pm = (const lds_u32*)(size_t)(addr + moff);
+            t[q][0] = p[0];
+            t[q][2] = p[RW];
+            tm[q][0] = pm[0];
+            tm[q][2] = pm[RW];
+            if (!F16) {
+                t[q][1] = p[1];
+                t[q][3] = p[RW + 1];
+                tm[q][1] = pm[1];
+                tm[q][3] = pm[RW + 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            float h0, h1, m0, m1;
+            if (F16) {
+                h0 = lerp_pair_f16(t[q][0], fu);
+                h1 = lerp_pair_f16(t[q][2], fu);
+                m0 = lerp_pair_f16(tm[q][0], fu);
+                m1 = lerp_pair_f16(tm[q][2], fu);
+            } else {
+                const float p00 = __builtin_bit_cast(float, t[q][0]), p01 = __builtin_bit_cast(float, t[q][1]);
+                const float p10 = __builtin_bit_cast(float, t[q][2]), p11 = __builtin_bit_cast(float, t[q][3]);
+                const float q00 = __builtin_bit_cast(float, tm[q][0]), q01 = __builtin_bit_cast(float, tm[q][1]);
+                const float q10 = __builtin_bit_cast(float, tm[q][2]), q11 = __builtin_bit_cast(float, tm[q][3]);
+                h0 = fmaf(fu, p01 - p00, p00);
+                h1 = fmaf(fu, p11 - p10, p10);
+                m0 = fmaf(fu, q01 - q00, q00);
+                m1 = fmaf(fu, q11 - q10, q10);
+            }
+            acc[g0 + q] = fmaf(W, fmaf(fv[q], h1 - h0, h0), acc[g0 + q]);
+            acc[H + g0 + q] = fmaf(W, fmaf(fv[q], m1 - m0, m0), acc[H + g0 + q]);
+        }
+    }
+}
+
+// Symmetric variant of the back-projector (Section 3.1.2) for geometries with
+// v(nz - 1 - k) = nh - 1 - v(k) (circular orbit, detector row centre at the
+// orbit plane, volume centred on it): a block owns KZ/2 slices of the lower
+// half of the volume and their mirrors.  Per view it stages the direct window
+// (rows r0 ..) in LDS region 0 and the mirrored one (rows nh - 1 - r0, nh -
+// 2 - r0, ..) in region 1, then runs the paired updates; a window taller than
+// one region is staged alone over the whole tile, direct then mirrored.
+template <int KZ, int PITCH, bool F16>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bp_sym_kernel(const BpArgs A)
+{
+    static_assert(KZ % 2 == 0, "slices are paired");
+    constexpr int H = KZ / 2;
+    constexpr int RW = TileRow<PITCH, F16>::W;
+    extern __shared__ float smem[];
+    float* tile = smem;                                       // [rows][PITCH] words
+    ViewRec* vtab = reinterpret_cast<ViewRec*>(smem + A.rows * PITCH);
+
+    const BlockPos bp = block_position(blockIdx.x, A.ntiles_pad);
+    const int t_id = bp.tile, chunk_local = bp.chunk_local;
+    if (t_id >= A.ntiles) return;                             // padding block
+    const int tx = t_id % A.ntx, ty = t_id / A.ntx;
+    const int kc = chunk_local * H;                           // first direct slice
+    const int i0 = tx * kTile, j0 = ty * kTile;
+    const int ni = min(kTile, A.nx - i0), nj = min(kTile, A.ny - j0);
+
+    const int tid = threadIdx.x;
+    const int wave = uniform(tid >> 6), lane = tid & 63;
+    const int lx = tid & (kTile - 1), ly = tid >> 4;
+    const bool active = lx < ni && ly < nj;
+    const float di = (float)min(lx, ni - 1), dj = (float)min(ly, nj - 1);
+
+    const char* proj = reinterpret_cast<const char*>(A.proj);
+    const unsigned row_bytes = (unsigned)A.nw * (F16 ? 2u : 4u);
+    const unsigned view_bytes = row_bytes * (unsigned)A.nh;
+    const unsigned tile_base = lds_addr(tile);
+    const int rr = A.rows / 2;                                // rows per region
+    float* mtile = tile + rr * RW;                            // region 1
+    const unsigned moff = 4u * (unsigned)(rr * RW);
+
+    float acc[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) acc[kk] = 0.f;
+
+    for (int sb = 0; sb < A.np; sb += kViewBatch) {
+        const int nb = min(kViewBatch, A.np - sb);
+        __syncthreads();
+        if (tid < nb) {
+            const int s = sb + tid;
+            const float sc = A.scale ? A.scale[s] : 1.0f;
+            view_record_sym(A.M + 12 * (size_t)s, i0, j0, ni, nj, kc, KZ, sc, PITCH, rr, &vtab[tid]);
+        }
+        __syncthreads();
+        for (int qv = 0; qv < nb; ++qv) {
+            const ViewRec& rv = vtab[qv];
+            const int c0 = uniform(rv.c0), C = uniform(rv.C);
+            const int r0 = uniform(rv.r0), R = uniform(rv.R);
+            const bool split = uniform(rv.split) != 0;
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(proj + (size_t)(sb + qv) * view_bytes), 0, (int)view_bytes, kBufferFlags);
+            stage_rows<PITCH, F16>(tile, A.rows, rs, A.nh, row_bytes, A.nw, r0, c0, R, C, wave, lane);
+            if (!split)
+                stage_rows<PITCH, F16, true>(mtile, A.rows, rs, A.nh, row_bytes, A.nw, A.nh - 1 - r0, c0,
+                                             R, C, wave, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const float w = fmaf(uniform(rv.d), di, fmaf(uniform(rv.e), dj, uniform(rv.w0)));
+            float F = __builtin_amdgcn_rcpf(w);
+            F = F * fmaf(-w, F, 2.0f);                        // one Newton step
+            const float u = fmaf(uniform(rv.a), di, fmaf(uniform(rv.b), dj, uniform(rv.N0))) * F;
+            const float dv = uniform(rv.m12) * F;
+            const float W = F * F * uniform(rv.scale);
+            const float fu = __builtin_amdgcn_fractf(u);
+            unsigned base;
+            if (F16) {
+                const int j = (int)u + (c0 & 1);
+                base = tile_base + 4u * (unsigned)((j >> 1) + ((j & 1) ? A.rows * (PITCH / 2) : 0));
+            } else {
+                base = tile_base + 4u * (unsigned)(int)u;
+            }
+            const HalfBase& hb = rv.half[0];
+            const float v0 = fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
+            if (!split) {
+                update_pair<KZ, PITCH, F16>(acc, base, moff, v0, dv, fu, W);
+            } else {
+                update_half<KZ, PITCH, F16>(acc, 0, base, v0, dv, fu, W);
+                __syncthreads();
+                stage_rows<PITCH, F16, true>(tile, A.rows, rs, A.nh, row_bytes, A.nw, A.nh - 1 - r0, c0,
+                                             R, C, wave, lane);
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                update_half<KZ, PITCH, F16>(acc, H, base, v0, dv, fu, W);
+            }
+            __syncthreads();                                  // tile is overwritten next
+        }
+    }
+
+    // ---- one read-modify-write per direct slice and per mirror
+    if (active) {
+        const int i = i0 + lx, j = j0 + ly;
+#pragma unroll
+        for (int t = 0; t < H; ++t) {
+            const int kd = kc + t, km = A.nz - 1 - kd;
+            if (kd <= km) {
+                float* dst = A.vol + ((size_t)kd * A.ny + j) * A.nx + i;
+                *dst += acc[t];
+            }
+            if (km > kd) {
+                float* dst = A.vol + ((size_t)km * A.ny + j) * A.nx + i;
+                *dst += acc[H + t];
+            }
         }
     }
 }
@@ -367,6 +540,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
 }
 
 template <int KZ, int PITCH>
+fdk_status launch_sym_pitch(const BpArgs& a, bool f16, size_t lds, unsigned blocks, hipStream_t st)
+{
+    const void* fn = f16 ? (const void*)bp_sym_kernel<KZ, PITCH, true>
+                         : (const void*)bp_sym_kernel<KZ, PITCH, false>;
+    if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(FDK_E_DEVICE, "cannot raise the LDS limit of the back-projection kernel");
+    }
+    if (f16)
+        hipLaunchKernelGGL((bp_sym_kernel<KZ, PITCH, true>), dim3(blocks), dim3(kThreads), lds, st, a);
+    else
+        hipLaunchKernelGGL((bp_sym_kernel<KZ, PITCH, false>), dim3(blocks), dim3(kThreads), lds, st, a);
+    return check_launch("symmetric back-projection kernel");
+}
+
+template <int KZ>
+fdk_status launch_sym_kz(const BpArgs& a, int pitch, bool f16, size_t lds, unsigned blocks, hipStream_t st)
+{
+    switch (pitch) {
+        case 40: return launch_sym_pitch<KZ, 40>(a, f16, lds, blocks, st);
+        case 56: return launch_sym_pitch<KZ, 56>(a, f16, lds, blocks, st);
+        case 72: return launch_sym_pitch<KZ, 72>(a, f16, lds, blocks, st);
+        case 88: return launch_sym_pitch<KZ, 88>(a, f16, lds, blocks, st);
+        case 120: return launch_sym_pitch<KZ, 120>(a, f16, lds, blocks, st);
+        case 184: return launch_sym_pitch<KZ, 184>(a, f16, lds, blocks, st);
+        case 248: return launch_sym_pitch<KZ, 248>(a, f16, lds, blocks, st);
+    }
+    return fail(FDK_E_UNSUPPORTED, "no kernel for this LDS pitch");
+}
+
+template <int KZ, int PITCH>
 fdk_status launch_kz_pitch(const BpArgs& a, bool f16, size_t lds, unsigned blocks, hipStream_t st)
 {
     const void* fn = f16 ? (const void*)bp_kernel<KZ, PITCH, true>
@@ -429,6 +633,38 @@ fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* strea
         case 8: return launch_kz<8>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
         case 16: return launch_kz<16>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
         case 32: return launch_kz<32>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
+    }
+    return fail(FDK_E_UNSUPPORTED, "no kernel for this slice count");
+}
+
+fdk_status launch_backproject_sym(const BpLaunch& a, const BpPlan& plan, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    fdk_status s = launch_compose(a.mats_world, a.mats_index, a.np, a.dx, a.dy, a.dz, a.ox, a.oy,
+                                  a.oz, stream);
+    if (s != FDK_OK) return s;
+    const int h = plan.kz / 2;
+    const int nch = ((a.nz + 1) / 2 + h - 1) / h;            // chunks of direct slices
+    BpArgs A;
+    A.proj = a.proj;
+    A.scale = a.scale;
+    A.M = a.mats_index;
+    A.vol = a.vol;
+    A.nx = a.nx; A.ny = a.ny; A.nz = a.nz; A.np = a.np; A.nh = a.nh; A.nw = a.nw;
+    A.k_begin = 0;
+    A.k_end = a.nz;
+    A.ntx = plan.ntx;
+    A.ntiles = plan.ntx * plan.nty;
+    A.ntiles_pad = plan.ntiles_pad;
+    A.chunk_first = 0;
+    A.rows = plan.rows;
+    const size_t lds = (size_t)plan.lds_bytes;
+    const int64_t blocks = (int64_t)plan.ntiles_pad * nch;
+    if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "grid too large");
+    switch (plan.kz) {
+        case 8: return launch_sym_kz<8>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
+        case 16: return launch_sym_kz<16>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
+        case 32: return launch_sym_kz<32>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
     }
     return fail(FDK_E_UNSUPPORTED, "no kernel for this slice count");
 }

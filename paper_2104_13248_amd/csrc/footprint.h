@@ -126,6 +126,62 @@ __device__ inline void view_record(const double* __restrict__ m, int i0, int j0,
     out->pad = 0;
 }
 
+// Record of the symmetric variant (Section 3.1.2): the block's kz / 2 direct
+// slices kc .. kc + kz/2 - 1 and their mirrors nz - 1 - k.  With v(nz-1-k) =
+// nh - 1 - v(k) the mirrored slices read the mirror image of the direct
+// window, rows nh - 1 - r0 - q for q = 0 .. R - 1, which the kernel stages in
+// that (descending) order, so a mirrored update uses the same window-relative
+// row and weight as its direct partner.  `split` is set when the window is
+// taller than one of the two LDS regions (region_rows): the two windows are
+// then staged one after the other over the whole tile.  half[1] and r1, R1
+// are unused.
+__device__ inline void view_record_sym(const double* __restrict__ m, int i0, int j0, int ni,
+                                       int nj, int kc, int kz, float scale, int pitch_max,
+                                       int region_rows, ViewRec* out)
+{
+    const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
+    const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
+    double umin = 1e300, umax = -1e300;
+#pragma unroll 1
+    for (int a = 0; a < 2; ++a)
+#pragma unroll 1
+        for (int b = 0; b < 2; ++b) {
+            const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
+            umin = fmin(umin, u);
+            umax = fmax(umax, u);
+        }
+    const double fu0 = floor(umin), fu1 = floor(umax);
+    const int c0 = (int)fu0 - 1;
+    int C = (int)(fu1 - fu0) + 4;
+    C = C < pitch_max ? C : pitch_max;
+    const int h2 = kz / 2;
+    int ra, Ra;
+    footprint_rows(m, ii, jj, (double)kc, (double)(kc + h2 - 1), &ra, &Ra);
+    const double w0 = m[8] * i0 + m[9] * j0 + m[11];
+    out->c0 = c0;
+    out->C = C;
+    out->d = (float)m[8];
+    out->e = (float)m[9];
+    out->w0 = (float)w0;
+    out->a = (float)(m[0] - c0 * m[8]);
+    out->b = (float)(m[1] - c0 * m[9]);
+    out->N0 = (float)((m[0] * i0 + m[1] * j0 + m[3]) - c0 * w0);
+    out->half[0].g = (float)(m[4] - ra * m[8]);
+    out->half[0].h = (float)(m[5] - ra * m[9]);
+    out->half[0].V0 = (float)((m[4] * i0 + m[5] * j0 + m[6] * (double)kc + m[7]) - ra * w0);
+    out->half[0].row = 0;
+    out->half[1] = out->half[0];
+    const int rmax = 2 * region_rows;
+    out->r0 = ra;
+    out->R = Ra < rmax ? Ra : rmax;
+    out->split = Ra > region_rows ? 1 : 0;
+    out->r1 = 0;
+    out->R1 = 0;
+    out->m12 = (float)m[6];
+    out->scale = scale;
+    out->pad = 0;
+}
+
 // Block id -> (chunk, tile).  Chunk-major so that resident blocks cover a thin
 // z-slab; blocks are dealt to the 8 XCDs round-robin by id, so XCD x gets the
 // contiguous band of tiles [x per, (x+1) per) of every chunk.

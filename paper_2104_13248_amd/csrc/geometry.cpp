@@ -291,6 +291,80 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
     return FDK_OK;
 }
 
+// Plan of the symmetric variant: a block owns kz / 2 direct slices and their
+// mirrors, and per view stages the direct window and its mirror image in two
+// LDS regions of rr rows; two regions must hold every half-chunk window (a
+// taller one is staged alone over the whole tile).  Budget 38 KiB (four
+// blocks per CU).
+fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
+                            const std::vector<IndexMatrix>& M, BpPlan& plan)
+{
+    (void)sg;
+    const int kz_force = env_int("FDK_BP_KZ", 0);
+    const int lds_budget = env_int("FDK_BP_SYM_LDS_BUDGET", 38 * 1024);
+    const int cands[3] = {32, 16, 8};
+    const int table_bytes = kViewBatch * kViewRec * 4;
+    BpPlan best;
+    bool found = false;
+    int64_t best_bytes = 0;
+    for (int q = 0; q < 3; ++q) {
+        const int kz = cands[q];
+        if (kz_force && kz != kz_force) continue;
+        Extent e = footprint(vg, M, kz);
+        int pitch = 0;
+        for (int p = 0; p < kNumPitches; ++p)
+            if (kPitches[p] >= e.cols) { pitch = kPitches[p]; break; }
+        if (!pitch) continue;
+        const int rr_budget = (lds_budget - table_bytes) / (2 * pitch * 4);
+        const int rr = std::max((e.rows_half + 1) / 2, std::min(rr_budget, e.rows_half));
+        const int64_t bytes = (int64_t)2 * rr * pitch * 4 + table_bytes;
+        if (bytes > 150 * 1024) continue;
+        if (!found || (best_bytes > lds_budget && bytes < best_bytes)) {
+            best.kz = kz;
+            best.pitch = pitch;
+            best.rows = 2 * rr;
+            best.rows_full = e.rows_full;
+            best.cols = e.cols;
+            best.lds_bytes = bytes;
+            best_bytes = bytes;
+            found = true;
+        }
+        if (found && best_bytes <= lds_budget) break;
+    }
+    if (!found)
+        return fail(FDK_E_UNSUPPORTED,
+                    "projection footprint of a 16x16x8 voxel block does not fit in LDS "
+                    "(magnification too large for the detector pitch)");
+    best.ntx = (vg.nx + kTile - 1) / kTile;
+    best.nty = (vg.ny + kTile - 1) / kTile;
+    best.ntiles_pad = ((best.ntx * best.nty + 7) / 8) * 8;
+    best.nchunks = ((vg.nz + 1) / 2 + best.kz / 2 - 1) / (best.kz / 2);
+    best.blocks = (int64_t)best.ntiles_pad * best.nchunks;
+    plan = best;
+    return FDK_OK;
+}
+
+// v(i, j, k) + v(i, j, nz - 1 - k) = nh - 1 for all i, j, k iff, with
+// v w = m4 i + m5 j + m6 k + m7 and w = m8 i + m9 j + m11 (m10 = 0):
+// 2 m4 = (nh - 1) m8, 2 m5 = (nh - 1) m9, 2 m7 + (nz - 1) m6 = (nh - 1) m11.
+bool bp_geometry_symmetric(const fdk_volume& vg, const fdk_stack& sg,
+                           const std::vector<IndexMatrix>& M)
+{
+    const double h = (double)(sg.nh - 1), z = (double)(vg.nz - 1);
+    auto close = [](double a, double b, double scale) {
+        return std::fabs(a - b) <= 1e-10 * scale;
+    };
+    for (size_t s = 0; s < M.size(); ++s) {
+        const double* m = M[s].m;
+        const double scale = std::fabs(m[4]) + std::fabs(m[5]) + std::fabs(m[6]) * (z + 1.0) +
+                             std::fabs(m[7]) + h * (std::fabs(m[8]) + std::fabs(m[9]) + std::fabs(m[11]));
+        if (!close(2.0 * m[4], h * m[8], scale) || !close(2.0 * m[5], h * m[9], scale) ||
+            !close(2.0 * m[7] + z * m[6], h * m[11], scale))
+            return false;
+    }
+    return true;
+}
+
 void fp_swap_flags(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
                    std::vector<int32_t>& swap)
 {

@@ -83,6 +83,15 @@ struct BpLaunch {
     int f16;
 };
 fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* stream);
+// Symmetric variant (whole volume; geometry checked by the caller with
+// bp_geometry_symmetric) and its launch plan.
+fdk_status launch_backproject_sym(const BpLaunch& a, const BpPlan& plan, void* stream);
+fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
+                            const std::vector<IndexMatrix>& M, BpPlan& plan);
+// Whether v(i, j, nz-1-k) = nh - 1 - v(i, j, k) for every view (index-space
+// matrices, relative tolerance 1e-10).
+bool bp_geometry_symmetric(const fdk_volume& vg, const fdk_stack& sg,
+                           const std::vector<IndexMatrix>& M);
 
 // Forward projector: a block per (band of rb detector rows, chunk of columns, view).
 struct FpPlan {

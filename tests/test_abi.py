@@ -287,3 +287,12 @@ def test_variant_entry_point_validates():
     s16 = _lib.stack_struct(C1["np"], C1["nh"], C1["nw"], _lib.FDK_F16)
     assert lib.fdk_backproject_variant(1, 4, ctypes.byref(vg), FAKE, ctypes.byref(s16), FAKE,
                                        _lib.ptr(m), None) == E_UNSUPPORTED
+    # the symmetric variant needs v(nz-1-k) = nh-1-v(k): rejected (before any HIP
+    # call) when the detector's centre row is offset or the volume is off-centre in z
+    m_off = np.ascontiguousarray(og.scan_matrices(dict(C1["scan"], v_off=1.5), C1["np"], C1["nh"],
+                                                  C1["nw"]))
+    assert lib.fdk_backproject_variant(3, 1, ctypes.byref(vg), FAKE, ctypes.byref(sg), FAKE,
+                                       _lib.ptr(m_off), None) == E_GEOMETRY
+    vz = _lib.volume_struct(C1["shape"], C1["voxel"], (0.0, 0.0, 2.0))
+    assert lib.fdk_backproject_variant(3, 1, ctypes.byref(vz), FAKE, ctypes.byref(sg), FAKE,
+                                       _lib.ptr(m), None) == E_GEOMETRY

@@ -114,8 +114,11 @@ fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k
  * around its (u, v) with the interpolation weights of Listing 2; taps outside
  * the detector are dropped.  vol: device float32 [nz][ny][nx]; proj: device
  * float32 [np][nh][nw] (sg->dtype must be FDK_F32, else FDK_E_UNSUPPORTED),
- * accumulated into.  Each projection sample is summed by one thread in a
- * fixed order (no atomics): the result is deterministic.  Views whose u
+ * accumulated into.  Each projection sample is summed by one block in a
+ * fixed order (no atomics): the result is deterministic.  Where the slices
+ * one tile of voxels reads would span 2 GiB or more of the volume (very large
+ * slices at steep cone angles), a slower organisation of the same sum is
+ * used.  Views whose u
  * changes faster along y than along x read a transposed copy of the volume,
  * a stream-ordered device allocation of the volume's size made by the call.
  * Same geometry requirement as above.
@@ -189,12 +192,13 @@ fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, const fdk_stack
 
 /*
  * fdk_bp_plan -- host query of the launch the back-projector would use for
- * these inputs: out[0..9] = tile_x, tile_y, kz (slices per thread),
+ * these inputs: out[0..11] = tile_x, tile_y, kz (slices per thread),
  * lds_pitch (words per LDS row), lds_rows, lds_bytes per block, blocks,
  * threads per block, rows_full (rows of the tallest whole-chunk footprint;
  * taller than lds_rows means such footprints are staged per half-chunk),
- * forward-projector lds_bytes per block.  Validates exactly like
- * fdk_backproject.  No HIP call.
+ * then the forward projector's lds_bytes per block, detector rows per band
+ * and detector columns per chunk.  out: host int64 [12].  Validates exactly
+ * like fdk_backproject.  No HIP call.
  */
 fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, const double* mats,
                        int64_t* out);

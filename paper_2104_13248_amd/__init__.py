@@ -158,11 +158,11 @@ def phantom_project(ell, scan: dict, proj: torch.Tensor, view_begin: int = 0,
 def bp_plan(shape, voxel, np_views, nh, nw, mats, centre=(0.0, 0.0, 0.0), f16=False) -> dict:
     """Launch configuration the back-projector would choose (host only)."""
     import ctypes
-    out = (ctypes.c_int64 * 10)()
+    out = (ctypes.c_int64 * 12)()
     m = _mats(mats, np_views)
     check(lib.fdk_bp_plan(volume_struct(shape, voxel, centre),
                           stack_struct(np_views, nh, nw, FDK_F16 if f16 else FDK_F32), ptr(m),
                           ctypes.cast(out, ctypes.c_void_p)))
     keys = ("tile_x", "tile_y", "kz", "lds_pitch", "lds_rows", "lds_bytes", "blocks", "threads",
-            "rows_full", "fp_lds_bytes")
+            "rows_full", "fp_lds_bytes", "fp_rows", "fp_cols")
     return dict(zip(keys, [int(x) for x in out]))

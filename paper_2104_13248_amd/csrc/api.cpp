@@ -51,8 +51,11 @@ extern "C" fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, con
     out[7] = kThreads;
     out[8] = plan.rows_full;
     FpPlan fpp;
-    s = make_fp_plan(*vg, *sg, fpp);
+    std::vector<int32_t> lanes;
+    s = make_fp_plan(*vg, *sg, M, lanes, fpp);
     out[9] = s == FDK_OK ? fpp.lds_bytes : 0;
+    out[10] = s == FDK_OK ? fpp.rb : 0;
+    out[11] = s == FDK_OK ? fpp.cw : 0;
     return FDK_OK;
 }
 
@@ -126,27 +129,26 @@ extern "C" fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
     if (!vol) return fail(FDK_E_INVALID, "volume pointer is NULL");
     if (!proj) return fail(FDK_E_INVALID, "projection pointer is NULL");
     FpPlan plan;
-    s = make_fp_plan(*vg, *sg, plan);
+    std::vector<int32_t> lanes;
+    s = make_fp_plan(*vg, *sg, M, lanes, plan);
     if (s != FDK_OK) return s;
-    std::vector<int32_t> swap;
-    fp_swap_flags(*vg, M, swap);
     bool any_swap = false;
-    for (int32_t f : swap) any_swap = any_swap || f;
+    for (int32_t f : lanes) any_swap = any_swap || (f & 1);
     const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
     const size_t vbytes = (size_t)vg->nx * vg->ny * vg->nz * sizeof(float);
     void* d_world = nullptr;
     void* d_index = nullptr;
-    void* d_swap = nullptr;
+    void* d_lanes = nullptr;
     void* d_volT = nullptr;
     s = upload_async(mats, mbytes, stream, &d_world);
-    if (s == FDK_OK) s = upload_async(swap.data(), swap.size() * sizeof(int32_t), stream, &d_swap);
+    if (s == FDK_OK) s = upload_async(lanes.data(), lanes.size() * sizeof(int32_t), stream, &d_lanes);
     if (s == FDK_OK) s = device_alloc_async(mbytes, stream, &d_index);
     if (s == FDK_OK && any_swap) s = device_alloc_async(vbytes, stream, &d_volT);
     if (s == FDK_OK) {
         FpLaunch a;
         a.vol = vol;
         a.volT = (float*)d_volT;
-        a.swap = (const int*)d_swap;
+        a.lanes = (const int*)d_lanes;
         a.proj = proj;
         a.mats_world = (const double*)d_world;
         a.mats_index = (double*)d_index;
@@ -157,7 +159,7 @@ extern "C" fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
         s = launch_forwardproject(a, plan, stream);
     }
     fdk_status s2 = FDK_OK;
-    for (void* d : {d_volT, d_index, d_swap, d_world})
+    for (void* d : {d_volT, d_index, d_lanes, d_world})
         if (d) {
             fdk_status e = device_free_async(d, stream);
             if (s2 == FDK_OK) s2 = e;

@@ -365,17 +365,33 @@ bool bp_geometry_symmetric(const fdk_volume& vg, const fdk_stack& sg,
     return true;
 }
 
-void fp_swap_flags(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
-                   std::vector<int32_t>& swap)
+void fp_view_lanes(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
+                   std::vector<int32_t>& lanes)
 {
     const double ic = 0.5 * (vg.nx - 1), jc = 0.5 * (vg.ny - 1);
-    swap.resize(M.size());
+    lanes.resize(M.size());
     for (size_t s = 0; s < M.size(); ++s) {
         const double* m = M[s].m;
-        const double w = m[8] * ic + m[9] * jc + m[11];
-        const double u = (m[0] * ic + m[1] * jc + m[3]) / w;
-        const double dui = (m[0] - u * m[8]) / w, duj = (m[1] - u * m[9]) / w;
-        swap[s] = std::fabs(duj) > std::fabs(dui) ? 1 : 0;
+        const double wc = m[8] * ic + m[9] * jc + m[11];
+        const double uc = (m[0] * ic + m[1] * jc + m[3]) / wc;
+        const double dui = (m[0] - uc * m[8]) / wc, duj = (m[1] - uc * m[9]) / wc;
+        const int sw = std::fabs(duj) > std::fabs(dui) ? 1 : 0;
+        const double ua = sw ? m[1] : m[0], ub = sw ? m[0] : m[1];
+        const double wa = sw ? m[9] : m[8], wb = sw ? m[8] : m[9];
+        const int na = sw ? vg.ny : vg.nx, nb = sw ? vg.nx : vg.ny;
+        // u = (ua a + U(b)) / (wa a + W(b)): du/da = (ua W(b) - wa U(b)) / w^2
+        auto N = [&](double b) { return ua * (wb * b + m[11]) - wa * (ub * b + m[3]); };
+        const double n0 = N(0.0), n1 = N((double)(nb - 1));
+        double wmax = 0.0;
+        for (double a : {0.0, (double)(na - 1)})
+            for (double b : {0.0, (double)(nb - 1)}) wmax = std::max(wmax, wa * a + wb * b + m[11]);
+        int64_t S = na;   // one voxel per pass: always free of collisions
+        if (n0 != 0.0 && n1 != 0.0 && (n0 > 0.0) == (n1 > 0.0)) {
+            const double slope = std::min(std::fabs(n0), std::fabs(n1)) / (wmax * wmax);
+            const double need = std::ceil(2.0001 / slope);
+            if (need < (double)na) S = std::max<int64_t>(1, (int64_t)need);
+        }
+        lanes[s] = (int32_t)((S << 1) | sw);
     }
 }
 

@@ -95,24 +95,32 @@ bool bp_geometry_symmetric(const fdk_volume& vg, const fdk_stack& sg,
 
 // Forward projector: a block per (band of rb detector rows, chunk of columns, view).
 struct FpPlan {
+    bool voxel = true;   // voxel-driven lanes (else one thread per detector column)
     int rb = 0;          // detector rows per band
-    int pitch = 0;       // LDS window pitch (columns per chunk + 2)
+    int cw = 0;          // detector columns per chunk
+    int pitch = 0;       // LDS window pitch (cw + 2)
     int nbands = 0;
     int ncb = 0;         // column chunks
     int64_t lds_bytes = 0;
     int64_t blocks = 0;
 };
-fdk_status make_fp_plan(const fdk_volume& vg, const fdk_stack& sg, FpPlan& plan);
-int64_t fp_lds_bytes(int rb, int nw);
+// Plan of one forward projection; also fills lanes (fp_view_lanes).  The
+// voxel-driven organisation unless FDK_FP_ALGO=gather or its load offsets
+// would not fit 31 bits for some view.
+fdk_status make_fp_plan(const fdk_volume& vg, const fdk_stack& sg, const std::vector<IndexMatrix>& M,
+                        std::vector<int32_t>& lanes, FpPlan& plan);
 
-// Views whose lanes should run along y: |du/dj| > |du/di| at the volume centre.
-void fp_swap_flags(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
-                   std::vector<int32_t>& swap);
+// Per view (S << 1) | swap.  swap: lanes run along y (|du/dj| > |du/di| at the
+// volume centre).  S: lane stride of the voxel-driven forward projector, the
+// smallest with |u(a + S) - u(a)| >= 2 columns along the lane axis anywhere in
+// the volume (|du/da| = |N(b)| / w^2 with N affine in the other index b).
+void fp_view_lanes(const fdk_volume& vg, const std::vector<IndexMatrix>& M,
+                   std::vector<int32_t>& lanes);
 
 struct FpLaunch {
     const float* vol;
     float* volT;             // scratch [nz][nx][ny] when any view swaps, else nullptr
-    const int* swap;         // device [np]
+    const int* lanes;        // device [np], from fp_view_lanes
     float* proj;
     const double* mats_world;
     double* mats_index;

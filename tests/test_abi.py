@@ -122,7 +122,7 @@ def test_tilted_detector_rejected():
     m3 = m.copy()
     m3[0, 0, 2] = 1e-16                      # round-off sized entries are accepted
     vg2 = _lib.volume_struct(C1["shape"], C1["voxel"])
-    out = (ctypes.c_int64 * 10)()
+    out = (ctypes.c_int64 * 12)()
     assert _lib.lib.fdk_bp_plan(ctypes.byref(vg2), ctypes.byref(sg), _lib.ptr(m3),
                                 ctypes.cast(out, ctypes.c_void_p)) == OK
 
@@ -238,10 +238,13 @@ def test_plan_covers_every_footprint(name):
     assert half <= plan["lds_rows"]
     assert full <= plan["rows_full"]
     assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4
-    # forward projector: a window of (band rows + 2) x (nw + 2) floats, within the default budget
-    fp = plan["fp_lds_bytes"]
-    pitch = min(cfg["nw"], 256) + 2
-    assert fp % (4 * pitch) == 0 and fp // (4 * pitch) >= 3
+    # forward projector: a window of (band rows + 2) x (chunk columns + 2) floats within the
+    # default budget; chunks of at most 240 columns cover the detector evenly
+    fp, rb, cw = plan["fp_lds_bytes"], plan["fp_rows"], plan["fp_cols"]
+    chunks = -(-cfg["nw"] // cw)
+    assert cw <= 240 and chunks == -(-cfg["nw"] // 240) and (chunks - 1) * cw < cfg["nw"]
+    assert fp % (4 * (rb + 2)) == 0 and cw + 4 <= fp // (4 * (rb + 2)) <= 254
+    assert 1 <= rb <= min(64, cfg["nh"])
     assert fp <= 16 * 1024
 
 

@@ -70,8 +70,7 @@ def test_forward_projection_many_bands(case, small_fp_budget):
     name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
     scan = dict(wl.CONFIGS[name]["scan"], **over)
     mats = og.scan_matrices(scan, npv, nh, nw)
-    rb = fdk.bp_plan(shape, (1.0, 1.0, 1.0), npv, nh, nw, mats, centre)["fp_lds_bytes"] \
-        // (4 * (min(nw, 256) + 2)) - 2
+    rb = fdk.bp_plan(shape, (1.0, 1.0, 1.0), npv, nh, nw, mats, centre)["fp_rows"]
     assert rb < nh // 3
     x = wl.gaussian(540 + case, shape)
     got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
@@ -201,3 +200,40 @@ def test_fdk_pipeline_on_gpu():
     e = rel(vol.cpu().numpy(), ref)
     log("pipeline rel-L2", e)
     assert e <= 1e-5
+
+
+@pytest.fixture
+def gather_organisation(monkeypatch):
+    """The column-owned organisation the library falls back to when the
+    voxel-driven kernel's load offsets would not fit (huge slices)."""
+    monkeypatch.setenv("FDK_FP_ALGO", "gather")
+
+
+@pytest.mark.parametrize("case", range(len(FP_CASES)))
+def test_forward_projection_gather_organisation(case, gather_organisation):
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
+    scan = dict(wl.CONFIGS[name]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    assert fdk.bp_plan(shape, (1.0, 1.0, 1.0), npv, nh, nw, mats, centre)["fp_cols"] == min(nw, 256)
+    x = wl.gaussian(590 + case, shape)
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    assert rel(got, ref) <= TOL32
+
+
+@pytest.mark.parametrize("voxel,pitch", [(0.25, 1.4), (2.5, 0.5)])
+def test_forward_projection_lane_strides(voxel, pitch):
+    """Pixels much wider than the magnified voxel (several voxels per column:
+    lane strides of 4 and more) and much narrower (five columns per voxel:
+    stride 1), both at a 45-degree view where neither axis dominates."""
+    scan = dict(sod=300.0, sdd=600.0, du=pitch, dv=pitch, arc=0.5 * math.pi,
+                theta0=0.25 * math.pi, u_off=0.5, v_off=-0.5)
+    shape, npv = (24, 40, 36), 9
+    nh = nw = int(2.6 * 40 * voxel / pitch) + 8
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    x = wl.gaussian(600, shape)
+    got = gpu_fp(x, mats, nh, nw, (voxel,) * 3)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (voxel,) * 3)
+    e = rel(got, ref)
+    log("fp lane strides", voxel, pitch, nh, "rel-L2", e)
+    assert e <= TOL32

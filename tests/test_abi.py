@@ -299,3 +299,19 @@ def test_variant_entry_point_validates():
     vz = _lib.volume_struct(C1["shape"], C1["voxel"], (0.0, 0.0, 2.0))
     assert lib.fdk_backproject_variant(3, 1, ctypes.byref(vz), FAKE, ctypes.byref(sg), FAKE,
                                        _lib.ptr(m), None) == E_GEOMETRY
+
+
+def test_forward_projector_falls_back_for_huge_slices(monkeypatch):
+    """The voxel-driven forward projector addresses a tile's slices with 31-bit
+    byte offsets; 256 MiB slices (8192^2 voxels) cannot fit even a few, so the
+    plan takes the column-owned organisation (256-column chunks); 64 MiB
+    slices still fit.  FDK_FP_ALGO=gather forces the fallback."""
+    scan = dict(sod=750.0, sdd=1200.0, du=1.0, dv=1.0, arc=2 * math.pi, theta0=0.0,
+                u_off=0.0, v_off=0.0)
+    mats = og.scan_matrices(scan, 8, 1024, 1024)
+    huge = fdk.bp_plan((16, 8192, 8192), (0.05,) * 3, 8, 1024, 1024, mats)
+    big = fdk.bp_plan((16, 4096, 4096), (0.1,) * 3, 8, 1024, 1024, mats)
+    assert huge["fp_cols"] == 256 and huge["fp_lds_bytes"] == 4 * (huge["fp_rows"] + 2) * 258
+    assert big["fp_cols"] == 205
+    monkeypatch.setenv("FDK_FP_ALGO", "gather")
+    assert fdk.bp_plan((16, 4096, 4096), (0.1,) * 3, 8, 1024, 1024, mats)["fp_cols"] == 256

@@ -123,50 +123,77 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
 // power-of-two strides of the passes' writes across the banks.
 __device__ __forceinline__ int fpad(int e) { return e + (e >> 5); }
 
-// One Stockham pass of radix R after sub-transforms of length NS: butterfly j
-// reads elements j + r M/R, twiddles them by W_{NS R}^{(j mod NS) r}, and
-// writes (j / NS) NS R + (j mod NS) + r NS.
-template <int M, int R, int NS>
-__device__ __forceinline__ void stockham_pass(float2* buf, const float2* __restrict__ tw, int tid)
+// Twiddles w[r] = W^r, r = 1 .. R - 1, of one butterfly from one table entry
+// W: the others by at most three complex products (W^2 = W W, W^4 = W^2 W^2,
+// W^3 = W^2 W, W^5 = W^4 W, W^6 = W^4 W^2, W^7 = W^4 W^3).
+template <int R>
+__device__ __forceinline__ void twiddles(float2 W, float2 (&w)[R])
 {
-    constexpr int B = M / R;
-    constexpr int J = (B + kFilterThreads - 1) / kFilterThreads;
-    float2 v[J][R];
-#pragma unroll
-    for (int q = 0; q < J; ++q) {
-        const int j = tid + kFilterThreads * q;
-        if (j < B) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = buf[fpad(j + r * B)];
-            if constexpr (NS > 1) {
-                const int k = j % NS;
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw[k * r * (M / (NS * R))]);
-            }
-            dft<R>(v[q]);
-        }
+    w[1] = W;
+    if constexpr (R >= 4) {
+        w[2] = cmul(W, W);
+        w[3] = cmul(w[2], W);
     }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < J; ++q) {
-        const int j = tid + kFilterThreads * q;
-        if (j < B) {
-            const int d = (j / NS) * NS * R + j % NS;
-#pragma unroll
-            for (int r = 0; r < R; ++r) buf[fpad(d + r * NS)] = v[q][r];
-        }
+    if constexpr (R == 8) {
+        w[4] = cmul(w[2], w[2]);
+        w[5] = cmul(w[4], W);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
     }
-    __syncthreads();
 }
 
-// Forward length-M DFT of buf (natural order in and out).
-template <int M, int NS = 1>
-__device__ __forceinline__ void fft(float2* buf, const float2* __restrict__ tw, int tid)
+// Stockham passes of a length-M forward DFT (natural order in and out), from
+// sub-transform length NS on.  Pass of radix R after sub-transforms of length
+// NS: butterfly j reads elements j + r M/R, twiddles them by
+// W_{NS R}^{(j mod NS) r}, and writes (j / NS) NS R + (j mod NS) + r NS.  The
+// first pass reads through first(e) and the last writes through last(e, v)
+// (FIRST_LDS / LAST_LDS: whether those touch the LDS buffer, which decides the
+// barriers); the passes in between use the buffer.
+template <int M, int NS, bool FIRST_LDS, bool LAST_LDS, class First, class Last>
+__device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw, int tid,
+                                           First first, Last last)
 {
     if constexpr (NS < M) {
         constexpr int R = M / NS >= 8 ? 8 : M / NS;
-        stockham_pass<M, R, NS>(buf, tw, tid);
-        fft<M, NS * R>(buf, tw, tid);
+        constexpr bool is_first = NS == 1, is_last = NS * R == M;
+        constexpr bool load_lds = !is_first || FIRST_LDS;
+        constexpr bool store_lds = !is_last || LAST_LDS;
+        constexpr int B = M / R;
+        constexpr int J = (B + kFilterThreads - 1) / kFilterThreads;
+        float2 v[J][R];
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+            const int j = tid + kFilterThreads * q;
+            if (j < B) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (is_first) v[q][r] = first(j + r * B);
+                    else v[q][r] = buf[fpad(j + r * B)];
+                }
+                if constexpr (NS > 1) {
+                    float2 w[R];
+                    twiddles<R>(tw[(j % NS) * (M / (NS * R))], w);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+                }
+                dft<R>(v[q]);
+            }
+        }
+        if constexpr (load_lds && store_lds) __syncthreads();   // in place: all reads first
+#pragma unroll
+        for (int q = 0; q < J; ++q) {
+            const int j = tid + kFilterThreads * q;
+            if (j < B) {
+                const int d = (j / NS) * NS * R + j % NS;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (is_last) last(d + r * NS, v[q][r]);
+                    else buf[fpad(d + r * NS)] = v[q][r];
+                }
+            }
+        }
+        if constexpr (store_lds) __syncthreads();
+        fft_passes<M, NS * R, FIRST_LDS, LAST_LDS>(buf, tw, tid, first, last);
     }
 }
 
@@ -185,32 +212,35 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const Filter
     const float v0 = ((float)(int)(row0 % A.nh) - A.cv) * A.dv;
     const float v1 = ((float)(int)((row0 + 1) % A.nh) - A.cv) * A.dv;
     const float w0 = A.sdd2 + v0 * v0, w1 = A.sdd2 + v1 * v1;
-    for (int c = tid; c < M; c += kFilterThreads) {
+    // forward transform of z = a + i b, the two cosine-weighted rows (zero
+    // beyond nw), read straight from the stack by the first pass
+    auto weighted = [&](int c) {
         float a = 0.f, b = 0.f;
         if (c < A.nw) {
             const float umm = ((float)c - A.cu) * A.du;
             a = s0[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w0)));
             if (two) b = s1[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w1)));
         }
-        buf[fpad(c)] = make_float2(a, b);
-    }
-    __syncthreads();
-    fft<M>(buf, tw, tid);
-    // conj(Z H): H is real
-    for (int k = tid; k < M; k += kFilterThreads) {
+        return make_float2(a, b);
+    };
+    auto to_buf = [&](int e, float2 v) { buf[fpad(e)] = v; };
+    fft_passes<M, 1, false, true>(buf, tw, tid, weighted, to_buf);
+    // inverse transform as conj(FFT(conj(Z H))) (H is real and holds 1/M):
+    // the first pass reads conj(Z H), the last writes row a = Re, row b = -Im
+    // of the first nw outputs straight to the stack
+    auto conj_zh = [&](int k) {
         const float2 z = buf[fpad(k)];
         const float h = H[k];
-        buf[fpad(k)] = make_float2(z.x * h, -z.y * h);
-    }
-    __syncthreads();
-    fft<M>(buf, tw, tid);
-    // z * h = conj(FFT(conj(Z H))) / M (1/M is in H): row a = Re, row b = -Im
+        return make_float2(z.x * h, -z.y * h);
+    };
     float* d0 = A.out + row0 * A.nw;
-    for (int c = tid; c < A.nw; c += kFilterThreads) {
-        const float2 y = buf[fpad(c)];
-        d0[c] = y.x;
-        if (two) d0[A.nw + c] = -y.y;
-    }
+    auto to_rows = [&](int c, float2 y) {
+        if (c < A.nw) {
+            d0[c] = y.x;
+            if (two) d0[A.nw + c] = -y.y;
+        }
+    };
+    fft_passes<M, 1, true, false>(buf, tw, tid, conj_zh, to_rows);
 }
 
 // tw[e] = exp(-2 pi i e / M); H[k] = (1/M) (h0 + 2 sum_{odd n < nw} hs / n^2

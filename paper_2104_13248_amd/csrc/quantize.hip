@@ -40,10 +40,17 @@ __global__ __launch_bounds__(kQThreads) void absmax_kernel(const float* __restri
     if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
         const float4* p4 = reinterpret_cast<const float4*>(p);
         const int64_t n4 = npix / 4;
-        for (int64_t t = t0; t < n4; t += nthreads) {
-            const float4 x = p4[t];
-            m = fmaxf(m, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+        auto absmax4 = [](float4 x) {
+            return fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w)));
+        };
+        int64_t t = t0;
+        // four independent loads in flight per thread
+        for (; t + 3 * nthreads < n4; t += 4 * nthreads) {
+            const float4 x0 = p4[t], x1 = p4[t + nthreads];
+            const float4 x2 = p4[t + 2 * nthreads], x3 = p4[t + 3 * nthreads];
+            m = fmaxf(m, fmaxf(fmaxf(absmax4(x0), absmax4(x1)), fmaxf(absmax4(x2), absmax4(x3))));
         }
+        for (; t < n4; t += nthreads) m = fmaxf(m, absmax4(p4[t]));
         head = n4 * 4;
     }
     for (int64_t t = head + t0; t < npix; t += nthreads) m = fmaxf(m, fabsf(p[t]));
@@ -75,11 +82,30 @@ __global__ __launch_bounds__(kQThreads) void quantize_kernel(const float* __rest
     if (blockIdx.x == 0 && threadIdx.x == 0) scale[s] = sc;
     const float* p = in + (size_t)s * npix;
     uint16_t* o = out + (size_t)s * npix;
-    for (int64_t t = (int64_t)blockIdx.x * kQThreads + threadIdx.x; t < npix;
-         t += (int64_t)gridDim.x * kQThreads) {
-        const _Float16 h = (_Float16)(p[t] * inv);   // v_cvt_f16_f32, round to nearest even
-        o[t] = __builtin_bit_cast(uint16_t, h);
+    const int64_t t0 = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
+    const int64_t nthreads = (int64_t)gridDim.x * kQThreads;
+    // v_cvt_f16_f32: round to nearest even
+    auto half_bits = [inv](float x) {
+        return (unsigned)__builtin_bit_cast(uint16_t, (_Float16)(x * inv));
+    };
+    int64_t head = 0;
+    if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+        // eight pixels per thread: two 16-byte loads, one 16-byte store
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+        uint4* o8 = reinterpret_cast<uint4*>(o);
+        const int64_t n8 = npix / 8;
+        for (int64_t t = t0; t < n8; t += nthreads) {
+            const float4 a = p4[2 * t], b = p4[2 * t + 1];
+            uint4 h;
+            h.x = half_bits(a.x) | (half_bits(a.y) << 16);
+            h.y = half_bits(a.z) | (half_bits(a.w) << 16);
+            h.z = half_bits(b.x) | (half_bits(b.y) << 16);
+            h.w = half_bits(b.z) | (half_bits(b.w) << 16);
+            o8[t] = h;
+        }
+        head = n8 * 8;
     }
+    for (int64_t t = head + t0; t < npix; t += nthreads) o[t] = (uint16_t)half_bits(p[t]);
 }
 
 }  // namespace
@@ -98,7 +124,7 @@ fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16
     int64_t bmax = (npix + kQThreads * 16 - 1) / (kQThreads * 16);
     if (bmax < 1) bmax = 1;
     const int64_t bm = bmax < 16 ? bmax : 16;
-    int64_t bx = (npix + kQThreads * 8 - 1) / (kQThreads * 8);
+    int64_t bx = (npix + kQThreads * 32 - 1) / (kQThreads * 32);
     if (bx > 1024) bx = 1024;
     if (bx < 1) bx = 1;
     if (s == FDK_OK) {

@@ -204,7 +204,7 @@ __device__ __forceinline__ void add4(float* win, int col, const float x[4], cons
 
 // Voxel-driven organisation.  A block is one wave and owns an LDS window of
 // rb + 2 rows (band rows r0 - 1 .. r0 + rb) by the columns c0 - 1 .. c0 + cw
-// plus two trash columns.  For each volume row b, the voxels whose left u-tap
+// plus two spare columns.  For each volume row b, the voxels whose left u-tap
 // lies in columns c0 - 1 .. c0 + cw - 1 form an interval of the lane axis
 // (Moebius solve), which the wave covers in passes of 64 voxels spaced S
 // apart.  S is chosen per row so that u moves by at least two columns between
@@ -212,7 +212,7 @@ __device__ __forceinline__ void add4(float* win, int col, const float x[4], cons
 // disjoint and stay so for every slice (u does not depend on k), so the lanes'
 // read-modify-writes of the window never collide.  Each voxel's set-up (1/w,
 // u, its two column weights, v and dv) is done once per band, against once per
-// column and band in fp_kernel, and the slice loop is branch-free.
+// column and band in fp_kernel.
 //
 // Lanes take part in a slice's update only while their v lies in the band's
 // window (lanes without a voxel keep v < 0), so idle lanes cost no LDS

@@ -145,6 +145,30 @@ def test_adjoint_identity_on_gpu(case):
     assert abs(lhs - rhs) <= 1e-5 * scale
 
 
+def test_adjoint_identity_precision_workload_scale():
+    """<BP p, x> = <p, FP x> at the scale of the 1024^3 precision workload:
+    0.5 mm voxels, 64 views over 360 degrees, 2048^2 detector (4 MiB slices,
+    nine column chunks of the forward projector, views on both lane axes)."""
+    cfg = wl.CONFIGS["c3"]
+    npv = 64
+    mats = og.scan_matrices(cfg["scan"], npv, cfg["nh"], cfg["nw"])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    x = torch.randn(cfg["shape"], device="cuda", generator=g)
+    p = torch.randn((npv, cfg["nh"], cfg["nw"]), device="cuda", generator=g)
+    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, p, mats, cfg["voxel"])
+    fpx = torch.zeros_like(p)
+    fdk.forwardproject(x, fpx, mats, cfg["voxel"])
+    torch.cuda.synchronize()
+    lhs = float(torch.sum(vol.double() * x.double()))
+    rhs = float(torch.sum(p.double() * fpx.double()))
+    scale = float(vol.double().norm() * x.double().norm())
+    log("adjoint at 1024^3 x 64 x 2048^2", lhs, rhs, abs(lhs - rhs) / scale)
+    assert abs(lhs - rhs) <= 1e-5 * scale
+    assert float(fpx.abs().max()) > 0.0
+
+
 def test_filter_parity():
     cfg = wl.CONFIGS["c1"]
     ell = wl.config_ellipsoids(cfg, 0)

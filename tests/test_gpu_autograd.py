@@ -96,3 +96,26 @@ def test_batched_volumes_and_forward_project_grad():
     for b in range(B):
         ref = oracle.backproject(w[b].cpu().numpy(), g.mats, g.shape, g.voxel, g.centre)
         assert rel(vol.grad[b].cpu().numpy(), ref) <= 1e-5
+
+
+def test_differentiation_workload_full_batch():
+    """The differentiation workload at full size through the autograd pair: a
+    batch of 8 volumes of 256^3 (0.25 mm), 360 views, 384^2 detector.  With
+    vol = BP(p) and p.grad = FP(y) (the backward of <BP p, y>), every item
+    satisfies <BP p, y> = <p, FP y>."""
+    cfg = wl.CONFIGS["c4"]
+    g = Geometry.circular(cfg["shape"], cfg["voxel"], cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    B = cfg["batch"]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(4040)
+    p = torch.randn((B, g.np, g.nh, g.nw), device="cuda", generator=gen).requires_grad_(True)
+    y = torch.randn((B,) + g.shape, device="cuda", generator=gen)
+    vol = back_project(p, g)
+    assert vol.shape == (B,) + tuple(g.shape)
+    (vol * y).sum().backward()
+    for b in range(B):
+        lhs = float((vol[b].detach().double() * y[b].double()).sum())
+        rhs = float((p[b].detach().double() * p.grad[b].double()).sum())
+        scale = float(vol[b].detach().double().norm() * y[b].double().norm())
+        log("batch item", b, lhs, rhs, abs(lhs - rhs) / scale)
+        assert abs(lhs - rhs) <= 1e-5 * scale

@@ -14,7 +14,7 @@
 // circular convolution free of wrap-around over the nw outputs) is real, and
 // two weighted rows a, b packed as z = a + i b give z * h = (a * h) + i (b * h)
 // from one forward transform, a multiplication by H and one inverse transform.
-// A block owns such a pair of rows; the transforms are Stockham radix-8/4/2
+// A block owns such a pair of rows; the transforms are Stockham radix-16/8/4/2
 // passes in LDS (natural order in and out), the inverse taken as
 // conj(FFT(conj(.))) with 1/M and the FDK constants folded into H.  H and the
 // twiddle factors are built per call in FP64.  Longer rows use a direct
@@ -84,7 +84,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place forward DFT of R = 2, 4 or 8 points (kernel e^{-2 pi i n k / R}).
+// In-place forward DFT of R = 2, 4, 8 or 16 points (kernel e^{-2 pi i n k / R}).
 template <int R>
 __device__ __forceinline__ void dft(float2 (&v)[R])
 {
@@ -101,6 +101,28 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
         v[2] = make_float2(t0.x - t2.x, t0.y - t2.y);
         v[1] = make_float2(t1.x + t3.x, t1.y + t3.y);
         v[3] = make_float2(t1.x - t3.x, t1.y - t3.y);
+    } else if constexpr (R == 16) {
+        // X[k] = E[k] + W16^k O[k], X[k + 8] = E[k] - W16^k O[k]
+        float2 e[8], o[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            e[r] = v[2 * r];
+            o[r] = v[2 * r + 1];
+        }
+        dft<8>(e);
+        dft<8>(o);
+        constexpr float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f;
+        constexpr float h = 0.70710678118654752f;
+        const float2 w16[8] = {make_float2(1.f, 0.f), make_float2(c1, -s1), make_float2(h, -h),
+                               make_float2(s1, -c1), make_float2(0.f, -1.f), make_float2(-s1, -c1),
+                               make_float2(-h, -h), make_float2(-c1, -s1)};
+#pragma unroll
+        for (int k = 1; k < 8; ++k) o[k] = cmul(o[k], w16[k]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = make_float2(e[k].x + o[k].x, e[k].y + o[k].y);
+            v[k + 8] = make_float2(e[k].x - o[k].x, e[k].y - o[k].y);
+        }
     } else {
         // X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k]
         float2 e[4] = {v[0], v[2], v[4], v[6]};
@@ -124,8 +146,9 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
 __device__ __forceinline__ int fpad(int e) { return e + (e >> 5); }
 
 // Twiddles w[r] = W^r, r = 1 .. R - 1, of one butterfly from one table entry
-// W: the others by at most three complex products (W^2 = W W, W^4 = W^2 W^2,
-// W^3 = W^2 W, W^5 = W^4 W, W^6 = W^4 W^2, W^7 = W^4 W^3).
+// W: the others by at most four complex products (W^2 = W W, W^4 = W^2 W^2,
+// W^8 = W^4 W^4, W^3 = W^2 W, W^5 = W^4 W, W^6 = W^4 W^2, W^7 = W^4 W^3,
+// W^(8+r) = W^8 W^r).
 template <int R>
 __device__ __forceinline__ void twiddles(float2 W, float2 (&w)[R])
 {
@@ -134,11 +157,16 @@ __device__ __forceinline__ void twiddles(float2 W, float2 (&w)[R])
         w[2] = cmul(W, W);
         w[3] = cmul(w[2], W);
     }
-    if constexpr (R == 8) {
+    if constexpr (R >= 8) {
         w[4] = cmul(w[2], w[2]);
         w[5] = cmul(w[4], W);
         w[6] = cmul(w[4], w[2]);
         w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (R == 16) {
+        w[8] = cmul(w[4], w[4]);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
     }
 }
 
@@ -149,21 +177,21 @@ __device__ __forceinline__ void twiddles(float2 W, float2 (&w)[R])
 // first pass reads through first(e) and the last writes through last(e, v)
 // (FIRST_LDS / LAST_LDS: whether those touch the LDS buffer, which decides the
 // barriers); the passes in between use the buffer.
-template <int M, int NS, bool FIRST_LDS, bool LAST_LDS, class First, class Last>
+template <int M, int T, int NS, bool FIRST_LDS, bool LAST_LDS, class First, class Last>
 __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw, int tid,
                                            First first, Last last)
 {
     if constexpr (NS < M) {
-        constexpr int R = M / NS >= 8 ? 8 : M / NS;
+        constexpr int R = M / NS >= 16 ? 16 : M / NS;
         constexpr bool is_first = NS == 1, is_last = NS * R == M;
         constexpr bool load_lds = !is_first || FIRST_LDS;
         constexpr bool store_lds = !is_last || LAST_LDS;
         constexpr int B = M / R;
-        constexpr int J = (B + kFilterThreads - 1) / kFilterThreads;
+        constexpr int J = (B + T - 1) / T;
         float2 v[J][R];
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-            const int j = tid + kFilterThreads * q;
+            const int j = tid + T * q;
             if (j < B) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -182,7 +210,7 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
         if constexpr (load_lds && store_lds) __syncthreads();   // in place: all reads first
 #pragma unroll
         for (int q = 0; q < J; ++q) {
-            const int j = tid + kFilterThreads * q;
+            const int j = tid + T * q;
             if (j < B) {
                 const int d = (j / NS) * NS * R + j % NS;
 #pragma unroll
@@ -193,12 +221,16 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
             }
         }
         if constexpr (store_lds) __syncthreads();
-        fft_passes<M, NS * R, FIRST_LDS, LAST_LDS>(buf, tw, tid, first, last);
+        fft_passes<M, T, NS * R, FIRST_LDS, LAST_LDS>(buf, tw, tid, first, last);
     }
 }
 
+// Threads of the Fourier-domain filter's block: one per radix-16 butterfly.
 template <int M>
-__global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const FilterArgs A,
+constexpr int fft_threads() { return M / 16 < 64 ? 64 : (M / 16 > 256 ? 256 : M / 16); }
+
+template <int M>
+__global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const FilterArgs A,
                                                                     const float* __restrict__ H,
                                                                     const float2* __restrict__ tw,
                                                                     int64_t nrows)
@@ -224,7 +256,8 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const Filter
         return make_float2(a, b);
     };
     auto to_buf = [&](int e, float2 v) { buf[fpad(e)] = v; };
-    fft_passes<M, 1, false, true>(buf, tw, tid, weighted, to_buf);
+    constexpr int T = fft_threads<M>();
+    fft_passes<M, T, 1, false, true>(buf, tw, tid, weighted, to_buf);
     // inverse transform as conj(FFT(conj(Z H))) (H is real and holds 1/M):
     // the first pass reads conj(Z H), the last writes row a = Re, row b = -Im
     // of the first nw outputs straight to the stack
@@ -240,7 +273,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_fft_kernel(const Filter
             if (two) d0[A.nw + c] = -y.y;
         }
     };
-    fft_passes<M, 1, true, false>(buf, tw, tid, conj_zh, to_rows);
+    fft_passes<M, T, 1, true, false>(buf, tw, tid, conj_zh, to_rows);
 }
 
 // tw[e] = exp(-2 pi i e / M); H[k] = (1/M) (h0 + 2 sum_{odd n < nw} hs / n^2
@@ -336,9 +369,9 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
                            tw, H);
         s = check_launch("filter table kernel");
         if (s == FDK_OK) {
-            const dim3 g((unsigned)((rows + 1) / 2)), b(kFilterThreads);
+            const dim3 g((unsigned)((rows + 1) / 2));
             switch (M) {
-#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, b, 0, st, A, (const float*)H, (const float2*)tw, rows); break;
+#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, dim3(fft_threads<m>()), 0, st, A, (const float*)H, (const float2*)tw, rows); break;
                 FDK_FFT(16) FDK_FFT(32) FDK_FFT(64) FDK_FFT(128) FDK_FFT(256) FDK_FFT(512)
                 FDK_FFT(1024) FDK_FFT(2048) FDK_FFT(4096)
 #undef FDK_FFT

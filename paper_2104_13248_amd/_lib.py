@@ -42,7 +42,7 @@ class Stack(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libfdk.so not built: run `python -m paper_2104_13248_amd.build` "
+        raise ImportError("libfdk.so not built: run `python paper_2104_13248_amd/build.py` "
                           "(or __graft_entry__.build()) first")
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p

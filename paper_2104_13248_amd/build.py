@@ -1,7 +1,9 @@
 """Build libfdk.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-    python -m paper_2104_13248_amd.build            # incremental
-    python -m paper_2104_13248_amd.build --force    # rebuild everything
+    python paper_2104_13248_amd/build.py            # incremental
+    python paper_2104_13248_amd/build.py --force    # rebuild everything
+
+(run as a script: importing the package loads the library it builds).
 
 Objects go to ``_build/`` at the repository root; the shared library to
 ``paper_2104_13248_amd/libfdk.so`` (where the Python binding loads it).

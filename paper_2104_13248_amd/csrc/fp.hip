@@ -409,14 +409,18 @@ namespace {
 // Window geometry of one organisation: rb rows of a band from the LDS budget.
 fdk_status fp_layout(const fdk_stack& sg, bool voxel, FpPlan& plan)
 {
-    int64_t budget = voxel ? 12 * 1024 : 16 * 1024;
+    int64_t budget = voxel ? 10 * 1024 : 16 * 1024;
     if (const char* e = std::getenv("FDK_FP_LDS_BUDGET")) budget = std::atoll(e);
     int cw, ncb, pitch = 0;
     if (voxel) {
-        // chunks of at most 240 columns; the pitch, a template constant of at
-        // least cw + 4, keeps a voxel's taps (0, 1, pitch, pitch + 1 words)
-        // within the offsets of one LDS instruction pair
-        ncb = (sg.nw + 239) / 240;
+        // chunks of at most 128 columns (measured best: a row's voxels in a
+        // chunk then fill about one tile, and the 10 KB window leaves room for
+        // ~15 waves per CU); the pitch, a template constant of at least cw + 4,
+        // keeps a voxel's taps (0, 1, pitch, pitch + 1 words) within the
+        // offsets of one LDS instruction pair
+        int cmax = 128;
+        if (const char* e = std::getenv("FDK_FP_CHUNK")) cmax = std::max(16, std::min(240, std::atoi(e)));
+        ncb = (sg.nw + cmax - 1) / cmax;
         cw = (sg.nw + ncb - 1) / ncb;
         for (int p : kFpPitches)
             if (pitch == 0 && p >= cw + 4) pitch = p;

@@ -238,14 +238,14 @@ def test_plan_covers_every_footprint(name):
     assert half <= plan["lds_rows"]
     assert full <= plan["rows_full"]
     assert plan["lds_bytes"] >= plan["lds_rows"] * plan["lds_pitch"] * 4
-    # forward projector: a window of (band rows + 2) x (chunk columns + 2) floats within the
-    # default budget; chunks of at most 240 columns cover the detector evenly
+    # forward projector: a window of (band rows + 2) x pitch floats within the default
+    # budget; chunks of at most 128 columns cover the detector evenly
     fp, rb, cw = plan["fp_lds_bytes"], plan["fp_rows"], plan["fp_cols"]
     chunks = -(-cfg["nw"] // cw)
-    assert cw <= 240 and chunks == -(-cfg["nw"] // 240) and (chunks - 1) * cw < cfg["nw"]
+    assert cw <= 128 and chunks == -(-cfg["nw"] // 128) and (chunks - 1) * cw < cfg["nw"]
     assert fp % (4 * (rb + 2)) == 0 and cw + 4 <= fp // (4 * (rb + 2)) <= 254
     assert 1 <= rb <= min(64, cfg["nh"])
-    assert fp <= 16 * 1024
+    assert fp <= 10 * 1024
 
 
 def test_learned_filter_entry_points_validate():
@@ -312,6 +312,6 @@ def test_forward_projector_falls_back_for_huge_slices(monkeypatch):
     huge = fdk.bp_plan((16, 8192, 8192), (0.05,) * 3, 8, 1024, 1024, mats)
     big = fdk.bp_plan((16, 4096, 4096), (0.1,) * 3, 8, 1024, 1024, mats)
     assert huge["fp_cols"] == 256 and huge["fp_lds_bytes"] == 4 * (huge["fp_rows"] + 2) * 258
-    assert big["fp_cols"] == 205
+    assert big["fp_cols"] == 128
     monkeypatch.setenv("FDK_FP_ALGO", "gather")
     assert fdk.bp_plan((16, 4096, 4096), (0.1,) * 3, 8, 1024, 1024, mats)["fp_cols"] == 256

@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kK = 9;            // taps
 constexpr int kHalo = kK / 2;
+constexpr int kTo1 = 16;        // positions per thread of the 32 -> 1 layers
 constexpr int kCT = 256;         // threads per block
 
 // Launch shape of the layer kernel for COUT output channels: G wave-uniform
@@ -137,11 +138,13 @@ __global__ __launch_bounds__(ConvShape<COUT>::NT) void conv_kernel(
 
 // Layers with one input or one output channel move 32 channels of
 // activations per position against at most 9 x 32 multiply-adds, so they are
-// bound by memory, not arithmetic.  Each thread owns 4 consecutive positions
-// of one row and streams what it needs straight from memory (16-byte loads
-// where the row allows; neighbouring threads share the 4-sample halos through
-// the cache): nothing is staged, few registers are live and many waves stay
-// resident to cover the memory latency.
+// bound by memory, not arithmetic.  Each thread owns consecutive positions
+// of one row (4 for the 1 -> 32 layers, kTo1 = 16 for the 32 -> 1 layers,
+// whose 32 input channels make the 4-sample halos the larger share of the
+// loads) and streams what it needs straight from memory (16-byte loads where
+// the row allows; neighbouring threads share the halos through the cache):
+// nothing is staged, few registers are live and many waves stay resident to
+// cover the memory latency.
 
 // Whether every base pointer allows 16-byte accesses (with len % 4 == 0,
 // then so does every row).
@@ -165,6 +168,27 @@ __device__ __forceinline__ void load12(const float* __restrict__ row, int x0, in
     } else {
 #pragma unroll
         for (int e = 0; e < 12; ++e) {
+            const int x = x0 - 4 + e;
+            v[e] = (x >= 0 && x < len) ? row[x] : 0.f;
+        }
+    }
+}
+
+// Samples in[x0 - 4 .. x0 + N - 5] of one channel row (N a multiple of 4),
+// zero outside [0, len).
+template <int N>
+__device__ __forceinline__ void loadn(const float* __restrict__ row, int x0, int len, bool vec,
+                                      float (&v)[N])
+{
+    if (vec) {
+#pragma unroll
+        for (int q = 0; q < N / 4; ++q) {
+            const float4 a = *reinterpret_cast<const float4*>(row + x0 - 4 + 4 * q);
+            v[4 * q] = a.x; v[4 * q + 1] = a.y; v[4 * q + 2] = a.z; v[4 * q + 3] = a.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
             const int x = x0 - 4 + e;
             v[e] = (x >= 0 && x < len) ? row[x] : 0.f;
         }
@@ -221,29 +245,38 @@ __global__ __launch_bounds__(256) void conv_to1_kernel(const float* __restrict__
                                                        const float* add, float alpha, int relu,
                                                        float* out, int rows, int len, int nq)
 {
+    // kTo1 positions per thread: kTo1 + 8 samples per channel (two 4-sample halos)
+    constexpr int PP = kTo1, NV = kTo1 + 8;
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= (int64_t)rows * nq) return;
     const int r = (int)(g / nq);
-    const int x0 = 4 * (int)(g - (int64_t)r * nq);
+    const int x0 = PP * (int)(g - (int64_t)r * nq);
     const bool al = aligned16(in, out, mask, add) && (len & 3) == 0;
-    const bool vec = al && x0 >= 4 && x0 + 8 <= len;
+    const bool vec = al && x0 >= 4 && x0 + PP + 4 <= len;
     const float* src = in + (size_t)r * 32 * len;
-    float acc[4];
+    float acc[PP];
     const float b0 = bias ? bias[0] : 0.f;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) acc[p] = b0;
-#pragma unroll 4
+    for (int p = 0; p < PP; ++p) acc[p] = b0;
+#pragma unroll 2
     for (int i = 0; i < 32; ++i) {
-        float v[12];
-        load12(src + (size_t)i * len, x0, len, vec, v);
+        float v[NV];
+        loadn<NV>(src + (size_t)i * len, x0, len, vec, v);
 #pragma unroll
         for (int t = 0; t < kK; ++t) {
             const float wt = TRANS ? w[i * kK + (kK - 1 - t)] : w[i * kK + t];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) acc[p] = fmaf(wt, v[p + t], acc[p]);
+            for (int p = 0; p < PP; ++p) acc[p] = fmaf(wt, v[p + t], acc[p]);
         }
     }
-    store4(acc, (size_t)r * len + x0, x0, len, al && x0 + 4 <= len, mask, add, alpha, relu, out);
+#pragma unroll
+    for (int q = 0; q < PP / 4; ++q) {
+        float a4[4] = {acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+        const int xq = x0 + 4 * q;
+        if (xq < len)
+            store4(a4, (size_t)r * len + xq, xq, len, al && xq + 4 <= len, mask, add, alpha, relu,
+                   out);
+    }
 }
 
 // 1 channel -> 32: the first layer's forward, or (TRANS) the last layer's
@@ -815,7 +848,7 @@ fdk_status conv_stream(int rows, int len, const float* in, const float* w, const
                        const float* mask, const float* add, float alpha, int relu, float* out,
                        hipStream_t st)
 {
-    const int nq = (len + 3) / 4;
+    const int nq = TO1 ? (len + kTo1 - 1) / kTo1 : (len + 3) / 4;   // threads per row
     const int64_t blocks = ((int64_t)rows * nq + 255) / 256;
     if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "conv1d tensor too large for one launch");
     if (TO1)

@@ -80,6 +80,26 @@ def test_forward_projection_many_bands(case, small_fp_budget):
     assert e <= TOL32
 
 
+@pytest.mark.parametrize("chunk", [16, 40])
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_forward_projection_narrow_chunks(case, chunk, monkeypatch):
+    """Column chunks of 16 or 40 detector columns, so that most voxels have
+    their two u-taps in neighbouring chunks (each chunk's window drops the
+    tap outside it and the neighbour adds it)."""
+    monkeypatch.setenv("FDK_FP_CHUNK", str(chunk))
+    name, shape, (npv, nh, nw), over, centre = FP_CASES[case]
+    scan = dict(wl.CONFIGS[name]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    cw = fdk.bp_plan(shape, (1.0, 1.0, 1.0), npv, nh, nw, mats, centre)["fp_cols"]
+    assert cw <= chunk and -(-nw // cw) >= 2
+    x = wl.gaussian(620 + case, shape)
+    got = gpu_fp(x, mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    ref = oracle.forwardproject(x.astype(np.float64), mats, nh, nw, (1.0, 1.0, 1.0), centre)
+    e = rel(got, ref)
+    log("fp narrow chunks", case, chunk, cw, "rel-L2", e)
+    assert e <= TOL32
+
+
 @pytest.mark.parametrize("theta0", [math.pi / 2 - 0.3, -0.3, 0.25 * math.pi - 0.3])
 def test_forward_projection_view_orientations(theta0):
     """Short arcs whose views all run lanes along x (no transposed copy), all

@@ -213,6 +213,41 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
     }
 }
 
+// Taps of update kk of a column for one view: the two pair words (binary16)
+// or four words (float32) around row floor(v), column floor(u); v >= 1 inside
+// the tile.
+template <int PITCH, bool F16>
+__device__ __forceinline__ void load_taps(unsigned base, float v, unsigned (&t)[4], float& fv)
+{
+    constexpr int RW = TileRow<PITCH, F16>::W;
+    fv = __builtin_amdgcn_fractf(v);
+    const lds_u32* p = (const lds_u32*)(size_t)(__umul24((unsigned)(int)v, 4u * RW) + base);
+    t[0] = p[0];
+    t[2] = p[RW];
+    if (!F16) {
+        t[1] = p[1];
+        t[3] = p[RW + 1];
+    }
+}
+
+// Bilinear value at (floor(u) + fu, floor(v) + fv) from the taps of load_taps
+// (Listing 2: horizontal lerps of the two rows, then the vertical one).
+template <bool F16>
+__device__ __forceinline__ float bilinear(const unsigned (&t)[4], float fu, float fv)
+{
+    float h0, h1;
+    if (F16) {
+        h0 = lerp_pair_f16(t[0], fu);
+        h1 = lerp_pair_f16(t[2], fu);
+    } else {
+        const float p00 = __builtin_bit_cast(float, t[0]), p01 = __builtin_bit_cast(float, t[1]);
+        const float p10 = __builtin_bit_cast(float, t[2]), p11 = __builtin_bit_cast(float, t[3]);
+        h0 = fmaf(fu, p01 - p00, p00);
+        h1 = fmaf(fu, p11 - p10, p10);
+    }
+    return fmaf(fv, h1 - h0, h0);
+}
+
 // KZ/2 consecutive updates kk = k0 + t, t = 0 .. KZ/2 - 1, of one column for
 // one view; v = v0 + t dv is the row coordinate relative to the half's origin,
 // whose LDS row address (plus the column) is `base`.  Tap loads run
@@ -227,34 +262,54 @@ __device__ __forceinline__ void update_half(float (&acc)[KZ], int k0, unsigned b
         float fv[kPrefetch];
         unsigned t[kPrefetch][4];
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) {
-            const float v = fmaf((float)(g0 + q), dv, v0);
-            fv[q] = __builtin_amdgcn_fractf(v);
-            // row floor(v) (v >= 1 inside the tile): one 24-bit multiply-add
-            constexpr int RW = TileRow<PITCH, F16>::W;
-            const lds_u32* p = (const lds_u32*)(size_t)(__umul24((unsigned)(int)v, 4u * RW) + base);
-            t[q][0] = p[0];
-            t[q][2] = p[RW];
-            if (!F16) {
-                t[q][1] = p[1];
-                t[q][3] = p[RW + 1];
-            }
-        }
+        for (int q = 0; q < kPrefetch; ++q)
+            load_taps<PITCH, F16>(base, fmaf((float)(g0 + q), dv, v0), t[q], fv[q]);
 #pragma unroll
-        for (int q = 0; q < kPrefetch; ++q) {
-            float h0, h1;
-            if (F16) {
-                h0 = lerp_pair_f16(t[q][0], fu);
-                h1 = lerp_pair_f16(t[q][2], fu);
-            } else {
-                const float p00 = __builtin_bit_cast(float, t[q][0]);
-                const float p01 = __builtin_bit_cast(float, t[q][1]);
-                const float p10 = __builtin_bit_cast(float, t[q][2]);
-                const float p11 = __builtin_bit_cast(float, t[q][3]);
-                h0 = fmaf(fu, p01 - p00, p00);
-                h1 = fmaf(fu, p11 - p10, p10);
-            }
-            acc[k0 + g0 + q] = fmaf(W, fmaf(fv[q], h1 - h0, h0), acc[k0 + g0 + q]);
+        for (int q = 0; q < kPrefetch; ++q)
+            acc[k0 + g0 + q] = fmaf(W, bilinear<F16>(t[q], fu, fv[q]), acc[k0 + g0 + q]);
+    }
+}
+
+// All KZ updates of one column for one view, in groups of two whose tap
+// loads are issued one group ahead: the two halves (row origins base0 /
+// base1, v origins v00 / v01) form one sequence.  When the footprint is
+// staged per half (`split`), `restage` replaces the window between the
+// halves and the second half's first loads wait for it; otherwise they are
+// in flight while the first half's last group is added.  A scheduling
+// barrier separates each group's loads from the previous group's arithmetic:
+// the scheduler would otherwise either hoist all loads (and run out of
+// registers) or sink them to their first use.
+template <int KZ, int PITCH, bool F16, typename Restage>
+__device__ __forceinline__ void update_column(float (&acc)[KZ], unsigned base0, unsigned base1,
+                                              float v00, float v01, float dv, float fu, float W,
+                                              bool split, Restage restage)
+{
+    constexpr int H = KZ / 2;
+    constexpr int G = 2;
+    constexpr int NG = KZ / G;
+    static_assert(H % G == 0, "groups do not straddle the halves");
+    unsigned t[2][G][4];
+    float fv[2][G];
+    auto load_group = [&](int g) {
+        const int k = g * G;
+        const unsigned b = k < H ? base0 : base1;
+        const float v0 = k < H ? v00 : v01;
+        const int t0 = k < H ? k : k - H;
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            load_taps<PITCH, F16>(b, fmaf((float)(t0 + q), dv, v0), t[g & 1][q], fv[g & 1][q]);
+    };
+    load_group(0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG && (g + 1 != NG / 2 || !split)) load_group(g + 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            acc[g * G + q] = fmaf(W, bilinear<F16>(t[g & 1][q], fu, fv[g & 1][q]), acc[g * G + q]);
+        if (g + 1 == NG / 2 && split) {
+            restage();
+            load_group(g + 1);
         }
     }
 }
@@ -506,20 +561,30 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             }
             // ---- hot loop: KZ updates of this column for this view, in two
             // halves; a footprint taller than the LDS tile is staged per half
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                if (q == 1 && uniform(rv.split)) {
-                    __syncthreads();
-                    stage_rows<PITCH, F16>(tile, A.rows, rs, A.nh, row_bytes, A.nw, uniform(rv.r1),
-                                           c0, uniform(rv.R1), C, wave, lane);
-                    __builtin_amdgcn_s_waitcnt(0);
-                    __syncthreads();
-                }
+            auto v_origin = [&](int q) {
                 const HalfBase& hb = rv.half[q];
-                const float v0 = fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
-                const unsigned row_base =
-                    base + (unsigned)(uniform(hb.row) * 4 * TileRow<PITCH, F16>::W);
-                update_half<KZ, PITCH, F16>(acc, q * (KZ / 2), row_base, v0, dv, fu, W);
+                return fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
+            };
+            auto row_base = [&](int q) {
+                return base + (unsigned)(uniform(rv.half[q].row) * 4 * TileRow<PITCH, F16>::W);
+            };
+            auto restage = [&] {
+                __syncthreads();
+                stage_rows<PITCH, F16>(tile, A.rows, rs, A.nh, row_bytes, A.nw, uniform(rv.r1), c0,
+                                       uniform(rv.R1), C, wave, lane);
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            };
+            if constexpr (F16) {
+                // one pipelined sequence over both halves
+                update_column<KZ, PITCH, F16>(acc, row_base(0), row_base(1), v_origin(0), v_origin(1),
+                                              dv, fu, W, uniform(rv.split) != 0, restage);
+            } else {
+                // (the float32 taps need twice the registers: the halves stay
+                // apart, which keeps the kernel within four waves per SIMD)
+                update_half<KZ, PITCH, F16>(acc, 0, row_base(0), v_origin(0), dv, fu, W);
+                if (uniform(rv.split)) restage();
+                update_half<KZ, PITCH, F16>(acc, KZ / 2, row_base(1), v_origin(1), dv, fu, W);
             }
             __syncthreads();                                  // tile is overwritten next
         }

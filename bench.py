@@ -328,7 +328,7 @@ def main() -> int:
     npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
     scan = cfg["scan"]
     mats = fdk.scan_matrices(scan, npv, nh, nw)
-    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], npv, nh, nw, mats)
+    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], npv, nh, nw, mats, f16=True)   # the FP16 step's launch
     log("config", args.config, cfg["shape"], (npv, nh, nw), "plan", plan)
 
     # ---- synthetic input, generated on the GPU (not timed)

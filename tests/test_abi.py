@@ -315,3 +315,29 @@ def test_forward_projector_falls_back_for_huge_slices(monkeypatch):
     assert big["fp_cols"] == 128
     monkeypatch.setenv("FDK_FP_ALGO", "gather")
     assert fdk.bp_plan((16, 4096, 4096), (0.1,) * 3, 8, 1024, 1024, mats)["fp_cols"] == 256
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c3", "c4", "c5"])
+def test_plan_tile_grows_to_four_blocks_per_cu(name, monkeypatch):
+    """Past the percentile footprint the back-projector's tile grows while four
+    blocks still fit a CU's 160 KiB of LDS (39 KiB each, view table included),
+    never beyond the tallest footprint; binary16 tiles take rows = 4 mod 8 so
+    that their two pair-word regions (rows x pitch/2 words each) start 16 banks
+    (mod 32) apart.  FDK_BP_TILE_BYTES=0 keeps the percentile rows."""
+    cfg = wl.CONFIGS[name]
+    m = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    args = (cfg["shape"], cfg["voxel"], cfg["np"], cfg["nh"], cfg["nw"], m)
+    table = 32 * 24 * 4
+    p32, p16 = fdk.bp_plan(*args), fdk.bp_plan(*args, f16=True)
+    monkeypatch.setenv("FDK_BP_TILE_BYTES", "0")
+    base = fdk.bp_plan(*args)
+    assert fdk.bp_plan(*args, f16=True)["lds_rows"] == base["lds_rows"]
+    for p in (p32, p16):
+        assert (p["kz"], p["lds_pitch"], p["rows_full"]) == (base["kz"], base["lds_pitch"], base["rows_full"])
+        assert p["lds_bytes"] == p["lds_rows"] * p["lds_pitch"] * 4 + table <= 39 * 1024
+        assert base["lds_rows"] <= p["lds_rows"]
+    fit = (39 * 1024 - table) // (base["lds_pitch"] * 4)
+    assert p32["lds_rows"] == max(base["lds_rows"], min(fit, base["rows_full"]))
+    if p16["lds_rows"] > base["lds_rows"]:
+        assert p16["lds_rows"] % 8 == 4 and p16["lds_rows"] <= fit
+        assert (p16["lds_rows"] * base["lds_pitch"] // 2) % 32 == 16

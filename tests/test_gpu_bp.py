@@ -161,8 +161,9 @@ def _sample_voxels(shape, n, seed):
 
 
 def test_c2_full_size_sampled():
-    """512^3 x 1024 views x 1024^2 (the benchmark launch), Gaussian
-    projections; sampled voxels against the oracle evaluated one by one."""
+    """512^3 x 1024 views x 1024^2 (the benchmark's shape) with float32
+    storage, Gaussian projections; sampled voxels against the oracle
+    evaluated one by one."""
     cfg = wl.CONFIGS["c2"]
     log("c2: generating", (cfg["np"], cfg["nh"], cfg["nw"]))
     proj = wl.gaussian(2001, (cfg["np"], cfg["nh"], cfg["nw"]))
@@ -179,6 +180,34 @@ def test_c2_full_size_sampled():
     ref = oracle.backproject_points(proj, mats, cfg["shape"], cfg["voxel"], ijk)
     e = rel(got, ref)
     log("c2 sampled rel-L2", e)
+    assert e <= TOL32
+
+
+def test_c2_full_size_sampled_f16():
+    """The benchmark launch itself: 512^3 x 1024 views x 1024^2 with binary16
+    storage and per-view scales (the plan's grown FP16 tile).  A seeded
+    binary16 stack is the input of both sides; sampled voxels against the
+    oracle evaluated one by one on the same values, to the FP32 tolerance."""
+    cfg = wl.CONFIGS["c2"]
+    shape, npv, nh, nw = cfg["shape"], cfg["np"], cfg["nh"], cfg["nw"]
+    log("c2 f16: generating", (npv, nh, nw))
+    h, s = wl.device_f16_stack(2002, (npv, nh, nw))
+    mats = og.scan_matrices(cfg["scan"], npv, nh, nw)
+    plan = fdk.bp_plan(shape, cfg["voxel"], npv, nh, nw, mats, f16=True)
+    log("c2 f16: plan", plan)
+    assert plan["lds_rows"] % 8 == 4
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, cfg["voxel"], scale=s)
+    torch.cuda.synchronize()
+    ijk = _sample_voxels(shape, 384, 17)
+    got = vol[ijk[:, 2], ijk[:, 1], ijk[:, 0]].cpu().numpy()
+    del vol
+    h_np, s_np = h.cpu().numpy(), s.cpu().numpy()
+    del h
+    log("c2 f16: oracle on", len(ijk), "voxels")
+    ref = oracle.backproject_points(h_np, mats, shape, cfg["voxel"], ijk, scale=s_np)
+    e = rel(got, ref)
+    log("c2 f16 sampled rel-L2", e)
     assert e <= TOL32
 
 

@@ -197,8 +197,9 @@ fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, const fdk_stack
  * threads per block, rows_full (rows of the tallest whole-chunk footprint;
  * taller than lds_rows means such footprints are staged per half-chunk),
  * then the forward projector's lds_bytes per block, detector rows per band
- * and detector columns per chunk.  out: host int64 [12].  Validates exactly
- * like fdk_backproject.  No HIP call.
+ * and detector columns per chunk.  The tile depends on sg->dtype (binary16
+ * tiles hold two regions of pair words).  out: host int64 [12].  Validates
+ * exactly like fdk_backproject.  No HIP call.
  */
 fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, const double* mats,
                        int64_t* out);

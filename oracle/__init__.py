@@ -5,7 +5,7 @@ CPU-baseline leg of ``bench.py`` use it.  The product library never imports,
 links or calls anything here, and nothing here imports the product package.
 
 The arithmetic lives in ``oracle.c`` (plain C, double precision, OpenMP over
-the loop the paper parallelises); this module only marshals numpy arrays into
+the voxels); this module only marshals numpy arrays into
 it.  ``geometry.py`` holds the closed-form circular-orbit matrices and
 ``quantize.py`` the FP16 storage rule.  Each function names the passage of
 Chen et al., ICS'21 ("Performance Portable Back-projection Algorithms on
@@ -55,7 +55,8 @@ def _load():
             stk = [_I64] * 3 + [_P] * 3
             lib.oracle_bp.argtypes = vol + stk + [_P, _P, ctypes.c_int]
             lib.oracle_bp_points.argtypes = vol + stk + [_P, _I64, _P, _P, ctypes.c_int]
-            lib.oracle_bp_block.argtypes = vol + stk + [_P] + [_I64] * 6 + [_P, ctypes.c_int]
+            lib.oracle_bp_block.argtypes = (vol + [_I64] * 5 + [_P] + [_P] * 3 + [_P] + [_I64] * 6
+                                            + [_P, ctypes.c_int])
             lib.oracle_bp_hoisted.argtypes = vol + stk + [_P, _P, ctypes.c_int]
             lib.oracle_bp_geometry.argtypes = vol + stk + [_D] * 8 + [_P, ctypes.c_int]
             lib.oracle_project_points.argtypes = [_D] * 5 + [_I64, _I64, _D, _D, _I64, _P, _P]
@@ -101,7 +102,8 @@ def max_threads() -> int:
 
 def backproject(proj, mats, shape, voxel, centre=(0.0, 0.0, 0.0), scale=None,
                 vol=None, threads=0):
-    """vol[nz,ny,nx] += sum_s bilinear(p_s, u, v) / w^2  (Listings 1-2), FP64.
+    """vol[nz,ny,nx] += sum_s p_s(u, v) / w^2 (Section 2.1.2), FP64; p_s(u, v)
+    is the tent-weighted (bilinear) value of view s, zero off the detector.
 
     ``mats`` are world-mm 3x4 matrices [np,3,4] applied to voxel centres.
     Returns the float64 volume (a new zero volume unless ``vol`` is given)."""
@@ -131,23 +133,38 @@ def backproject_points(proj, mats, shape, voxel, ijk, centre=(0.0, 0.0, 0.0),
 
 
 def backproject_block(proj, mats, shape, voxel, box, centre=(0.0, 0.0, 0.0),
-                      scale=None, threads=0):
-    """Back-projection of the sub-block box = ((k0,k1),(j0,j1),(i0,i1))."""
+                      scale=None, threads=0, origin=None, detector=None):
+    """Back-projection of the sub-block box = ((k0,k1),(j0,j1),(i0,i1)).
+
+    ``proj`` holds whole views ([np,nh,nw]), or, with ``origin`` ([np,2] int:
+    first detector row and column of each view's window) and ``detector``
+    ((nh, nw)), only a window of each view ([np,wr,wc]).  A window must hold
+    every detector pixel the block's voxels reach; if one does not, this
+    raises instead of returning an incomplete sum."""
     lib = _load()
     (k0, k1), (j0, j1), (i0, i1) = box
     mats = np.ascontiguousarray(mats, dtype=np.float64)
     out = np.zeros((k1 - k0, j1 - j0, i1 - i0), dtype=np.float64)
     stk, keep = _stack_args(proj, scale)
-    lib.oracle_bp_block(*_vol_args(shape, voxel, centre), *stk, _ptr(mats),
-                        int(i0), int(i1), int(j0), int(j1), int(k0), int(k1),
-                        _ptr(out), int(threads))
+    npv, wr, wc = stk[0], stk[1], stk[2]
+    if origin is None:
+        nh, nw, org = wr, wc, None
+    else:
+        nh, nw = (int(n) for n in detector)
+        org = np.ascontiguousarray(origin, dtype=np.int64).reshape(npv, 2)
+    miss = lib.oracle_bp_block(*_vol_args(shape, voxel, centre), npv, nh, nw, wr, wc,
+                               _ptr(org), *stk[3:], _ptr(mats),
+                               int(i0), int(i1), int(j0), int(j1), int(k0), int(k1),
+                               _ptr(out), int(threads))
     del keep
+    if miss:
+        raise ValueError("a voxel of the block reaches a detector pixel outside its view's window")
     return out
 
 
 def backproject_hoisted(proj, mats, shape, voxel, centre=(0.0, 0.0, 0.0), scale=None,
                         threads=0):
-    """Algorithm-1 loop order: u and w hoisted out of the k loop (Section 3.1.2)."""
+    """u and w computed once per voxel column and view (Section 3.1.2)."""
     lib = _load()
     mats = np.ascontiguousarray(mats, dtype=np.float64)
     vol = np.zeros(shape, dtype=np.float64)

@@ -6,47 +6,62 @@
  * leg of the benchmark do.  It shares no code, header, table or constant with
  * the HIP path.
  *
- * What it computes (Chen et al., ICS'21, Section 2.1.2, Listings 1 and 2):
+ * What it computes (Chen et al., ICS'21, Section 2.1.2 with the pinhole
+ * model of Section 2.1.1): every voxel receives, from every filtered view s,
+ * the view's value at the point where the voxel centre X projects, divided
+ * by the square of the projective depth:
  *
- *   vol[k][j][i] += sum_s  B_s(u_s, v_s) / w_s^2
- *   (u_s w_s, v_s w_s, w_s) = P_s (X(i), Y(j), Z(k), 1)^T
- *   B_s(u, v) = bilinear interpolation of view s at (u, v), zero outside
+ *   vol(X) += sum_s  p_s(u_s, v_s) / w_s^2,   (u_s w_s, v_s w_s, w_s) = P_s (X, 1)
  *
- * with the readings that the paper leaves open (they are listed in the
- * design notes of the repository as R1..R20):
+ * and the value between pixel centres is bilinear interpolation, written here
+ * as the tent-weighted sum it is:
+ *
+ *   p_s(u, v) = sum_{r, c} p_s[r][c] hat(u - c) hat(v - r),  hat(t) = max(0, 1 - |t|)
+ *
+ * Only the (at most) four pixels around (u, v) have a non-zero weight; a
+ * pixel that does not exist (outside [0,nh-1] x [0,nw-1]) is absent from the
+ * sum, i.e. contributes zero.
+ *
+ * Readings of what the paper leaves open (the repository's design notes list
+ * them as R1..R20):
  *   - P_s maps world millimetres (voxel centres) to homogeneous pixel
  *     coordinates; voxel (i,j,k) has its centre at
  *     ((i-(nx-1)/2) dx + cx, (j-(ny-1)/2) dy + cy, (k-(nz-1)/2) dz + cz);
  *   - pixel (r, c) of a view sits at (u, v) = (c, r); u runs along the
  *     detector width nw (fastest index), v along the height nh;
- *   - the integer part is the mathematical floor (the listing's (int) cast
- *     truncates, which equals floor only for non-negative coordinates);
- *   - a tap outside [0,nh-1] x [0,nw-1] contributes zero;
- *   - the weight is 1/w^2 exactly as the matrix gives w (Listing 1 squares
- *     f = 1/z);
- *   - accumulation is into the caller's volume (Listing 1 updates with +=).
+ *   - the four pixels are found with the mathematical floor (the paper's
+ *     code truncates, which equals floor only for non-negative coordinates);
+ *   - the weight is 1/w^2 exactly as the matrix gives w;
+ *   - results are added to the caller's volume.
  *
  * Every function works in double precision and takes no shortcut beyond what
  * the definition states.  The projection stack may be given as float32, or as
  * IEEE binary16 bit patterns with a per-view float32 scale (dequantised value
- * = half * scale); both convert exactly to double.
+ * = half * scale); both convert exactly to double.  A stack may also hold
+ * only a window of each view (rows r0_s .. r0_s + wr - 1, columns
+ * c0_s .. c0_s + wc - 1 of the nh x nw detector); a pixel inside the detector
+ * but outside its view's window is then reported as a miss (the caller chose
+ * too small a window) instead of being silently taken as zero.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
 #include <omp.h>
 
-/* ---- projection access (exact conversion to double) ------------------- */
+/* ---- the filtered views --------------------------------------------------- */
 
 typedef struct {
-    const float *f32;        /* [np][nh][nw] or NULL           */
-    const uint16_t *f16;     /* [np][nh][nw] binary16 or NULL   */
-    const float *scale;      /* [np] per-view scale for f16     */
-    int64_t nh, nw;
-} stack_t_;
+    const float *f32;        /* [np][wr][wc] or NULL            */
+    const uint16_t *f16;     /* [np][wr][wc] binary16 or NULL   */
+    const float *scale;      /* [np] per-view scale for binary16 */
+    int64_t nh, nw;          /* detector rows and columns        */
+    int64_t wr, wc;          /* stored rows and columns per view */
+    const int64_t *origin;   /* [np][2] (r0, c0) of each stored window; NULL: whole views */
+    int *miss;               /* set when a needed pixel lies outside its window */
+} views_t;
 
 /* IEEE 754 binary16 -> double, decoded from its definition. */
-static double half_to_double(uint16_t h)
+static double half_value(uint16_t h)
 {
     int sign = (h >> 15) & 1;
     int expo = (h >> 10) & 0x1f;
@@ -61,96 +76,127 @@ static double half_to_double(uint16_t h)
     return sign ? -mag : mag;
 }
 
-/* Pixel (r, c) of view s, zero outside the detector (zero extension). */
-static double tap(const stack_t_ *st, int64_t s, int64_t r, int64_t c)
+/* Pixel value p_s[r][c]; a pixel off the detector does not exist (zero). */
+static double pixel(const views_t *V, int64_t s, int64_t r, int64_t c)
 {
-    if (r < 0 || r >= st->nh || c < 0 || c >= st->nw)
+    if (r < 0 || r >= V->nh || c < 0 || c >= V->nw)
         return 0.0;
-    int64_t idx = (s * st->nh + r) * st->nw + c;
-    if (st->f32)
-        return (double)st->f32[idx];
-    return half_to_double(st->f16[idx]) * (double)st->scale[s];
+    if (V->origin) {
+        r -= V->origin[2 * s];
+        c -= V->origin[2 * s + 1];
+        if (r < 0 || r >= V->wr || c < 0 || c >= V->wc) {
+            #pragma omp atomic write
+            *V->miss = 1;
+            return 0.0;
+        }
+    }
+    int64_t idx = (s * V->wr + r) * V->wc + c;
+    if (V->f32)
+        return (double)V->f32[idx];
+    return half_value(V->f16[idx]) * (double)V->scale[s];
 }
 
-/* mix(x, y, a) = x (1 - a) + y a  (Listing 2) */
-static double mix(double x, double y, double a) { return x * (1.0 - a) + y * a; }
-
-/* Bilinear_Interpolate of Listing 2: horizontal blends of rows r and r+1,
- * then a vertical blend; floor instead of truncation, zero outside. */
-static double bilinear(const stack_t_ *st, int64_t s, double u, double v)
+/* Tent (hat) function: the weight of a pixel at distance t along one axis. */
+static double hat(double t)
 {
-    /* Far outside the detector every tap is zero; this also keeps the
-     * integer conversion below in range. */
-    if (!(u > -2.0 && u < (double)st->nw + 1.0 && v > -2.0 && v < (double)st->nh + 1.0))
+    double a = 1.0 - fabs(t);
+    return a > 0.0 ? a : 0.0;
+}
+
+/* Value of view s at detector point (u, v): the tent-weighted sum over the
+ * pixels around it.  The weights of pixels farther than one pitch vanish, so
+ * only the 2 x 2 pixels starting at (floor(v), floor(u)) are visited.  A
+ * point more than one pitch off the detector sees no pixel at all (this also
+ * keeps the integer conversion in range). */
+static double view_value(const views_t *V, int64_t s, double u, double v)
+{
+    if (!(u > -1.0 && u < (double)V->nw && v > -1.0 && v < (double)V->nh))
         return 0.0;
-    double cf = floor(u), rf = floor(v);
-    int64_t c = (int64_t)cf, r = (int64_t)rf;
-    double fu = u - cf, fv = v - rf;
-    double s0 = mix(tap(st, s, r, c), tap(st, s, r, c + 1), fu);
-    double s1 = mix(tap(st, s, r + 1, c), tap(st, s, r + 1, c + 1), fu);
-    return mix(s0, s1, fv);
+    double c_lo = floor(u), r_lo = floor(v);
+    double sum = 0.0;
+    for (int dr = 0; dr < 2; dr++)
+        for (int dc = 0; dc < 2; dc++) {
+            double r = r_lo + dr, c = c_lo + dc;
+            double wgt = hat(v - r) * hat(u - c);
+            if (wgt != 0.0)
+                sum += wgt * pixel(V, s, (int64_t)r, (int64_t)c);
+        }
+    return sum;
 }
 
-/* dot4 of Listing 2 with the homogeneous 1 implicit. */
-static double dot4(const double *row, double x, double y, double z)
+/* Homogeneous image (u w, v w, w) of the world point X under the 3x4 matrix
+ * P (row-major), Section 2.1.1. */
+static void image_of(const double *P, const double X[3], double h[3])
 {
-    return row[0] * x + row[1] * y + row[2] * z + row[3];
+    for (int row = 0; row < 3; row++) {
+        const double *p = P + 4 * row;
+        h[row] = p[0] * X[0] + p[1] * X[1] + p[2] * X[2] + p[3];
+    }
 }
+
+/* What view s adds to the voxel centred at X: p_s(u, v) / w^2. */
+static double view_term(const views_t *V, const double *mats, int64_t s, const double X[3])
+{
+    double h[3];
+    image_of(mats + 12 * s, X, h);
+    double w = h[2];
+    return view_value(V, s, h[0] / w, h[1] / w) / (w * w);
+}
+
+/* Sum over the views s = 0 .. np-1, in that order, for the voxel at X. */
+static double voxel_sum(const views_t *V, const double *mats, int64_t np, const double X[3])
+{
+    double acc = 0.0;
+    for (int64_t s = 0; s < np; s++)
+        acc += view_term(V, mats, s, X);
+    return acc;
+}
+
+/* ---- the voxel grid ------------------------------------------------------- */
 
 typedef struct {
     int64_t nx, ny, nz;
     double dx, dy, dz, cx, cy, cz;
-} volgeom_t;
+} grid_t;
 
-static double vx(const volgeom_t *g, int64_t i) { return ((double)i - 0.5 * (double)(g->nx - 1)) * g->dx + g->cx; }
-static double vy(const volgeom_t *g, int64_t j) { return ((double)j - 0.5 * (double)(g->ny - 1)) * g->dy + g->cy; }
-static double vz(const volgeom_t *g, int64_t k) { return ((double)k - 0.5 * (double)(g->nz - 1)) * g->dz + g->cz; }
-
-/* One voxel, one view, matrix mode: the body of Listing 1. */
-static double update_matrix(const stack_t_ *st, const double *mat, int64_t s,
-                            double X, double Y, double Z)
+/* World position (mm) of the centre of voxel (i, j, k). */
+static void voxel_centre(const grid_t *g, int64_t i, int64_t j, int64_t k, double X[3])
 {
-    const double *m = mat + 12 * s;
-    double z = dot4(m + 8, X, Y, Z);
-    double f = 1.0 / z;
-    double x = dot4(m + 0, X, Y, Z) * f;
-    double y = dot4(m + 4, X, Y, Z) * f;
-    double val = bilinear(st, s, x, y);
-    double w = f * f;
-    return val * w;
+    X[0] = ((double)i - 0.5 * (double)(g->nx - 1)) * g->dx + g->cx;
+    X[1] = ((double)j - 0.5 * (double)(g->ny - 1)) * g->dy + g->cy;
+    X[2] = ((double)k - 0.5 * (double)(g->nz - 1)) * g->dz + g->cz;
 }
 
-static void fill_stack(stack_t_ *st, int64_t nh, int64_t nw, const float *p32,
-                       const uint16_t *p16, const float *scale)
+static views_t whole_views(int64_t nh, int64_t nw, const float *p32, const uint16_t *p16,
+                           const float *scale)
 {
-    st->f32 = p32; st->f16 = p16; st->scale = scale; st->nh = nh; st->nw = nw;
+    views_t V = {p32, p16, scale, nh, nw, nh, nw, NULL, NULL};
+    return V;
 }
 
-/* ---- back-projection, matrix mode, Listing-1 loop order ---------------- */
-/* mats: [np][3][4] world-mm -> homogeneous pixel.  vol: [nz][ny][nx] += .   */
+/* ---- back-projection of the whole volume --------------------------------- */
+/* mats: [np][3][4] world mm -> homogeneous pixel.  vol: [nz][ny][nx] +=.     */
 int oracle_bp(int64_t nx, int64_t ny, int64_t nz,
               double dx, double dy, double dz, double cx, double cy, double cz,
               int64_t np, int64_t nh, int64_t nw,
               const float *p32, const uint16_t *p16, const float *scale,
               const double *mats, double *vol, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
-    stack_t_ st; fill_stack(&st, nh, nw, p32, p16, scale);
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    views_t V = whole_views(nh, nw, p32, p16, scale);
+    int64_t n = nx * ny * nz;
     if (nthreads > 0) omp_set_num_threads(nthreads);
-    for (int64_t s = 0; s < np; s++) {
-        #pragma omp parallel for schedule(static)
-        for (int64_t k = 0; k < nz; k++)
-            for (int64_t j = 0; j < ny; j++)
-                for (int64_t i = 0; i < nx; i++)
-                    vol[(k * ny + j) * nx + i] +=
-                        update_matrix(&st, mats, s, vx(&g, i), vy(&g, j), vz(&g, k));
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; q++) {
+        double X[3];
+        voxel_centre(&g, q % nx, (q / nx) % ny, q / (nx * ny), X);
+        vol[q] += voxel_sum(&V, mats, np, X);
     }
     return 0;
 }
 
-/* ---- back-projection of selected voxels (same arithmetic) -------------- */
-/* ijk: [n][3] voxel indices (i, j, k); out[n] = full sum over all views.
- * Views are summed in order s = 0..np-1 for every voxel, as above.          */
+/* ---- back-projection of selected voxels ----------------------------------- */
+/* ijk: [n][3] voxel indices (i, j, k); out[n] = the sum over all views.      */
 int oracle_bp_points(int64_t nx, int64_t ny, int64_t nz,
                      double dx, double dy, double dz, double cx, double cy, double cz,
                      int64_t np, int64_t nh, int64_t nw,
@@ -158,79 +204,87 @@ int oracle_bp_points(int64_t nx, int64_t ny, int64_t nz,
                      const double *mats, int64_t n, const int64_t *ijk,
                      double *out, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
-    stack_t_ st; fill_stack(&st, nh, nw, p32, p16, scale);
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    views_t V = whole_views(nh, nw, p32, p16, scale);
     if (nthreads > 0) omp_set_num_threads(nthreads);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t q = 0; q < n; q++) {
-        double X = vx(&g, ijk[3 * q]), Y = vy(&g, ijk[3 * q + 1]), Z = vz(&g, ijk[3 * q + 2]);
-        double acc = 0.0;
-        for (int64_t s = 0; s < np; s++)
-            acc += update_matrix(&st, mats, s, X, Y, Z);
-        out[q] = acc;
+        double X[3];
+        voxel_centre(&g, ijk[3 * q], ijk[3 * q + 1], ijk[3 * q + 2], X);
+        out[q] = voxel_sum(&V, mats, np, X);
     }
     return 0;
 }
 
-/* ---- back-projection of an axis-aligned sub-block ----------------------- */
-/* out: [k1-k0][j1-j0][i1-i0] += contributions of all views.                 */
+/* ---- back-projection of an axis-aligned sub-block ------------------------- */
+/* out: [k1-k0][j1-j0][i1-i0] += the sums over all views.  The stack holds
+ * wr x wc pixels per view; with origin != NULL they are the window of view s
+ * whose first pixel is detector pixel (origin[s][0], origin[s][1]), else the
+ * whole view (wr = nh, wc = nw).  Returns 1 if some voxel needed a detector
+ * pixel outside its view's window (the result is then incomplete), else 0.  */
 int oracle_bp_block(int64_t nx, int64_t ny, int64_t nz,
                     double dx, double dy, double dz, double cx, double cy, double cz,
-                    int64_t np, int64_t nh, int64_t nw,
+                    int64_t np, int64_t nh, int64_t nw, int64_t wr, int64_t wc,
+                    const int64_t *origin,
                     const float *p32, const uint16_t *p16, const float *scale,
                     const double *mats,
                     int64_t i0, int64_t i1, int64_t j0, int64_t j1, int64_t k0, int64_t k1,
                     double *out, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
-    stack_t_ st; fill_stack(&st, nh, nw, p32, p16, scale);
-    int64_t bx = i1 - i0, by = j1 - j0;
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    int miss = 0;
+    views_t V = {p32, p16, scale, nh, nw, wr, wc, origin, &miss};
+    int64_t bx = i1 - i0, by = j1 - j0, bz = k1 - k0;
+    int64_t n = bx * by * bz;
     if (nthreads > 0) omp_set_num_threads(nthreads);
-    for (int64_t s = 0; s < np; s++) {
-        #pragma omp parallel for schedule(static)
-        for (int64_t k = k0; k < k1; k++)
-            for (int64_t j = j0; j < j1; j++)
-                for (int64_t i = i0; i < i1; i++)
-                    out[((k - k0) * by + (j - j0)) * bx + (i - i0)] +=
-                        update_matrix(&st, mats, s, vx(&g, i), vy(&g, j), vz(&g, k));
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; q++) {
+        double X[3];
+        voxel_centre(&g, i0 + q % bx, j0 + (q / bx) % by, k0 + q / (bx * by), X);
+        out[q] += voxel_sum(&V, mats, np, X);
     }
-    return 0;
+    return miss;
 }
 
-/* ---- back-projection, matrix mode, Algorithm-1 order (hoisted) ---------- */
-/* For every column (i, j) and view s the depth w and the detector column u
- * are computed once and shared along k (Section 3.1.2, Algorithm 1); only
- * v is recomputed per k.  The value equals oracle_bp in exact arithmetic
- * provided the matrix has no k-dependence in rows 0 and 2 (the detector's
- * V-axis is parallel to the rotation axis, Section 2.1.1).                  */
+/* ---- back-projection with u and w computed once per column ---------------- */
+/* Section 3.1.2 / Algorithm 1: when neither u w nor w depends on z (the
+ * detector's V-axis parallel to the rotation axis, Section 2.1.1), the depth
+ * w and the column coordinate u of a voxel column (i, j) are the same for all
+ * its slices, and only v changes along k.  This evaluates the sum that way:
+ * w and u per (column, view), v per voxel.  It equals oracle_bp in exact
+ * arithmetic for such matrices, which the tests check.  Columns are
+ * independent; each voxel still sums its views in order s = 0 .. np-1.     */
 int oracle_bp_hoisted(int64_t nx, int64_t ny, int64_t nz,
                       double dx, double dy, double dz, double cx, double cy, double cz,
                       int64_t np, int64_t nh, int64_t nw,
                       const float *p32, const uint16_t *p16, const float *scale,
                       const double *mats, double *vol, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
-    stack_t_ st; fill_stack(&st, nh, nw, p32, p16, scale);
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    views_t V = whole_views(nh, nw, p32, p16, scale);
     if (nthreads > 0) omp_set_num_threads(nthreads);
-    #pragma omp parallel for collapse(2) schedule(static)
-    for (int64_t j = 0; j < ny; j++)
-        for (int64_t i = 0; i < nx; i++) {
-            double X = vx(&g, i), Y = vy(&g, j);
-            for (int64_t s = 0; s < np; s++) {
-                const double *m = mats + 12 * s;
-                double F = 1.0 / dot4(m + 8, X, Y, 0.0);     /* row 2, k-free */
-                double W = F * F;
-                double U = dot4(m + 0, X, Y, 0.0) * F;       /* row 0, k-free */
-                for (int64_t k = 0; k < nz; k++) {
-                    double V = dot4(m + 4, X, Y, vz(&g, k)) * F;
-                    vol[(k * ny + j) * nx + i] += bilinear(&st, s, U, V) * W;
-                }
+    #pragma omp parallel for schedule(static)
+    for (int64_t col = 0; col < nx * ny; col++) {
+        double X[3];
+        voxel_centre(&g, col % nx, col / nx, 0, X);
+        double base[3];
+        for (int64_t s = 0; s < np; s++) {
+            const double *P = mats + 12 * s;
+            X[2] = 0.0;
+            image_of(P, X, base);                      /* (u w, v w, w) at z = 0 */
+            double w = base[2];                        /* free of z              */
+            double u = base[0] / w;                    /* free of z              */
+            for (int64_t k = 0; k < nz; k++) {
+                double Z = ((double)k - 0.5 * (double)(nz - 1)) * dz + cz;
+                double v = (base[1] + P[6] * Z) / w;
+                vol[k * nx * ny + col] += view_value(&V, s, u, v) / (w * w);
             }
         }
+    }
     return 0;
 }
 
-/* ---- back-projection, geometry mode (no matrices) ----------------------- */
+/* ---- back-projection, geometry mode (no matrices) ------------------------- */
 /* Circular source orbit about +z (Section 2.1.1: the detector's V-axis is
  * parallel to the rotation axis).  View s is at angle theta_s =
  * theta0 + arc * s / np.  Source S = sod (cos, sin, 0); detector plane
@@ -242,7 +296,7 @@ int oracle_bp_hoisted(int64_t nx, int64_t ny, int64_t nz,
  * and the depth is the distance from the source to X along the central ray,
  * normalised so that it equals 1 at the isocentre: w = n.(S - X) / sod.      */
 static void project_geometry(double th, double sod, double sdd, double du, double dv,
-                             double cu, double cv, double X, double Y, double Z,
+                             double cu, double cv, const double X[3],
                              double *u, double *v, double *w)
 {
     double ct = cos(th), st_ = sin(th);
@@ -250,7 +304,7 @@ static void project_geometry(double th, double sod, double sdd, double du, doubl
     double C[3] = {-(sdd - sod) * ct, -(sdd - sod) * st_, 0.0};
     double n[3] = {ct, st_, 0.0};                 /* unit normal, source side */
     double eu[3] = {-st_, ct, 0.0}, ev[3] = {0.0, 0.0, 1.0};
-    double d[3] = {X - S[0], Y - S[1], Z - S[2]};
+    double d[3] = {X[0] - S[0], X[1] - S[1], X[2] - S[2]};
     double nd = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
     double ncs = n[0] * (C[0] - S[0]) + n[1] * (C[1] - S[1]) + n[2] * (C[2] - S[2]);
     double lam = ncs / nd;
@@ -259,7 +313,7 @@ static void project_geometry(double th, double sod, double sdd, double du, doubl
     double vmm = ev[0] * H[0] + ev[1] * H[1] + ev[2] * H[2];
     *u = umm / du + cu;
     *v = vmm / dv + cv;
-    *w = (n[0] * (S[0] - X) + n[1] * (S[1] - Y) + n[2] * (S[2] - Z)) / sod;
+    *w = (n[0] * (S[0] - X[0]) + n[1] * (S[1] - X[1]) + n[2] * (S[2] - X[2])) / sod;
 }
 
 int oracle_bp_geometry(int64_t nx, int64_t ny, int64_t nz,
@@ -270,20 +324,23 @@ int oracle_bp_geometry(int64_t nx, int64_t ny, int64_t nz,
                        double du, double dv, double u_off, double v_off,
                        double *vol, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
-    stack_t_ st; fill_stack(&st, nh, nw, p32, p16, scale);
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    views_t V = whole_views(nh, nw, p32, p16, scale);
     double cu = 0.5 * (double)(nw - 1) + u_off, cv = 0.5 * (double)(nh - 1) + v_off;
+    int64_t n = nx * ny * nz;
     if (nthreads > 0) omp_set_num_threads(nthreads);
-    for (int64_t s = 0; s < np; s++) {
-        double th = theta0 + arc * (double)s / (double)np;
-        #pragma omp parallel for schedule(static)
-        for (int64_t k = 0; k < nz; k++)
-            for (int64_t j = 0; j < ny; j++)
-                for (int64_t i = 0; i < nx; i++) {
-                    double u, v, w;
-                    project_geometry(th, sod, sdd, du, dv, cu, cv, vx(&g, i), vy(&g, j), vz(&g, k), &u, &v, &w);
-                    vol[(k * ny + j) * nx + i] += bilinear(&st, s, u, v) / (w * w);
-                }
+    #pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; q++) {
+        double X[3];
+        voxel_centre(&g, q % nx, (q / nx) % ny, q / (nx * ny), X);
+        double acc = 0.0;
+        for (int64_t s = 0; s < np; s++) {
+            double th = theta0 + arc * (double)s / (double)np;
+            double u, v, w;
+            project_geometry(th, sod, sdd, du, dv, cu, cv, X, &u, &v, &w);
+            acc += view_value(&V, s, u, v) / (w * w);
+        }
+        vol[q] += acc;
     }
     return 0;
 }
@@ -296,45 +353,46 @@ int oracle_project_points(double th, double sod, double sdd, double du, double d
 {
     double cu = 0.5 * (double)(nw - 1) + u_off, cv = 0.5 * (double)(nh - 1) + v_off;
     for (int64_t q = 0; q < n; q++)
-        project_geometry(th, sod, sdd, du, dv, cu, cv, xyz[3 * q], xyz[3 * q + 1], xyz[3 * q + 2],
+        project_geometry(th, sod, sdd, du, dv, cu, cv, xyz + 3 * q,
                          &out[3 * q], &out[3 * q + 1], &out[3 * q + 2]);
     return 0;
 }
 
-/* ---- forward projection: the exact transpose of oracle_bp -------------- */
-/* proj[s][r][c] += sum over voxels of vol * (1/w^2) * (bilinear weight of
- * tap (r, c) at the voxel's (u, v)); taps outside the detector are dropped,
- * exactly mirroring the zero extension of the back-projection.            */
+/* ---- forward projection: the exact transpose of oracle_bp ----------------- */
+/* Back-projection is linear in the pixels: voxel X receives
+ * sum_{s,r,c} p_s[r][c] hat(u_s - c) hat(v_s - r) / w_s^2.  Its transpose
+ * therefore gives every existing pixel (r, c) of view s the sum over voxels of
+ * x(X) hat(u_s - c) hat(v_s - r) / w_s^2, with the same (u, v, w) and the same
+ * pixels (those off the detector do not exist).  One thread owns a view, so
+ * no pixel has two writers; voxels are visited in index order.              */
 int oracle_fp(int64_t nx, int64_t ny, int64_t nz,
               double dx, double dy, double dz, double cx, double cy, double cz,
               int64_t np, int64_t nh, int64_t nw,
               const double *vol, const double *mats, double *proj, int nthreads)
 {
-    volgeom_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    grid_t g = {nx, ny, nz, dx, dy, dz, cx, cy, cz};
+    int64_t n = nx * ny * nz;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < np; s++) {
-        const double *m = mats + 12 * s;
-        double *P = proj + s * nh * nw;
-        for (int64_t k = 0; k < nz; k++)
-            for (int64_t j = 0; j < ny; j++)
-                for (int64_t i = 0; i < nx; i++) {
-                    double X = vx(&g, i), Y = vy(&g, j), Z = vz(&g, k);
-                    double f = 1.0 / dot4(m + 8, X, Y, Z);
-                    double u = dot4(m + 0, X, Y, Z) * f;
-                    double v = dot4(m + 4, X, Y, Z) * f;
-                    if (!(u > -2.0 && u < (double)nw + 1.0 && v > -2.0 && v < (double)nh + 1.0))
+        double *img = proj + s * nh * nw;
+        for (int64_t q = 0; q < n; q++) {
+            double X[3], h[3];
+            voxel_centre(&g, q % nx, (q / nx) % ny, q / (nx * ny), X);
+            image_of(mats + 12 * s, X, h);
+            double w = h[2], u = h[0] / w, v = h[1] / w;
+            if (!(u > -1.0 && u < (double)nw && v > -1.0 && v < (double)nh))
+                continue;
+            double x = vol[q] / (w * w);
+            double c_lo = floor(u), r_lo = floor(v);
+            for (int dr = 0; dr < 2; dr++)
+                for (int dc = 0; dc < 2; dc++) {
+                    double r = r_lo + dr, c = c_lo + dc;
+                    if (r < 0.0 || r >= (double)nh || c < 0.0 || c >= (double)nw)
                         continue;
-                    double cf = floor(u), rf = floor(v);
-                    int64_t c = (int64_t)cf, r = (int64_t)rf;
-                    double fu = u - cf, fv = v - rf;
-                    double x = vol[(k * ny + j) * nx + i] * f * f;
-                    double wt[4] = {(1 - fu) * (1 - fv), fu * (1 - fv), (1 - fu) * fv, fu * fv};
-                    int64_t rr[4] = {r, r, r + 1, r + 1}, cc[4] = {c, c + 1, c, c + 1};
-                    for (int t = 0; t < 4; t++)
-                        if (rr[t] >= 0 && rr[t] < nh && cc[t] >= 0 && cc[t] < nw)
-                            P[rr[t] * nw + cc[t]] += x * wt[t];
+                    img[(int64_t)r * nw + (int64_t)c] += x * hat(v - r) * hat(u - c);
                 }
+        }
     }
     return 0;
 }

@@ -247,6 +247,33 @@ def test_points_and_block_equal_full():
     np.testing.assert_array_equal(blk, full[2:6, 1:8, 3:9])
 
 
+def test_block_from_view_windows():
+    """A sub-block computed from per-view windows of the stack equals the
+    same block from whole views, bit for bit (same pixels, same order), at a
+    corner whose windows hang over the detector edges; a window one column
+    too narrow is refused rather than read as zeros."""
+    from oracle import window as owin
+    cfg = wl.shrink(wl.CONFIGS["c1"], shape=(12, 11, 13), np_views=7, nh=24, nw=26)
+    mats = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
+    proj = wl.gaussian(29, (cfg["np"], cfg["nh"], cfg["nw"]))
+    for box in (((0, 5), (0, 4), (0, 6)), ((4, 9), (3, 8), (5, 11)), ((7, 12), (6, 11), (8, 13))):
+        whole = oracle.backproject_block(proj, mats, cfg["shape"], cfg["voxel"], box)
+        origin, wr, wc = owin.block_windows(mats, cfg["shape"], cfg["voxel"], box)
+        win = owin.cut_windows(proj, origin, wr, wc)
+        got = oracle.backproject_block(win, mats, cfg["shape"], cfg["voxel"], box,
+                                       origin=origin, detector=(cfg["nh"], cfg["nw"]))
+        np.testing.assert_array_equal(got, whole)
+        assert np.abs(whole).max() > 0
+    mid = ((4, 9), (3, 8), (5, 11))
+    origin, wr, wc = owin.block_windows(mats, cfg["shape"], cfg["voxel"], mid, margin=0)
+    narrow = origin.copy()
+    narrow[:, 1] += 1                       # drops each window's first needed column
+    with pytest.raises(ValueError):
+        oracle.backproject_block(owin.cut_windows(proj, narrow, wr, wc), mats, cfg["shape"],
+                                 cfg["voxel"], mid, origin=narrow,
+                                 detector=(cfg["nh"], cfg["nw"]))
+
+
 def test_accumulates_into_volume():
     proj, mats, shape, voxel = tiny_problem()
     base = np.random.default_rng(4).standard_normal(shape)

@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of voxel-driven FDK back-projection on one MI355X.
 
-Workload (default): 512^3 volume (1 mm voxels), 1024 views over 360 degrees,
-1024 x 1024 detector (1 mm), SOD 750 mm, SDD 1200 mm; filtered projections of a
-seeded 40-ellipsoid phantom generated on the GPU (analytic line integrals +
-FDK ramp filter), volume zero-initialised.
+Workload (default, the FP16-storage metric's configuration): 1024^3 volume
+(0.5 mm voxels), 2048 views over 360 degrees, 2048 x 2048 detector (0.5 mm),
+SOD 750 mm, SDD 1200 mm; filtered projections of a seeded 60-ellipsoid
+phantom generated on the GPU (analytic line integrals + FDK ramp filter),
+stored once as float32 and once as binary16 with one power-of-two scale per
+view (written by the filter itself); volume zero-initialised.
 
-One step = zero the volume, FP16 storage pre-pass (per-view scale + binary16
-codes), back-projection of all views with FP32 coordinates and accumulation.
-The FP32-storage step (zero + back-projection of the float32 stack) is timed
-the same way and reported beside it.  GUPS = nx ny nz np / t / 1e9.
+One step = zero the volume, back-project all views with FP32 coordinates and
+accumulation.  Both storages are timed the same way; the binary16 one is the
+headline `value`, the float32 one is reported beside it.
+GUPS = nx ny nz np / t / 1e9 (Section 2.3).
 
-Prints ONE JSON line.  Also reports the dominant kernel against its roofline
-(timed with HIP events on the stream it runs on) and the FP64 oracle timed on
-the host's cores on a bounded sub-block of the same workload.
+After timing, the last volume of each storage is checked: rel-L2 of the
+binary16-storage volume against the float32-storage volume (whole volume),
+and of both against the FP64 oracle on eight 64^3 sub-blocks (centre, corners,
+edges), the oracle reading only each view's window of the same stacks.  The
+run fails (exit 3) if float32 storage is above 1e-5 or binary16 storage above
+1e-3 of the oracle.  The oracle's timing on those blocks is the CPU baseline.
+
+Prints ONE JSON line, with the dominant kernel against its rooflines (timed
+with HIP events on the stream it runs on) and the ceilings measured on the
+same GPU by the microbenchmarks of include/fdk_peaks.h.
 """
 from __future__ import annotations
 
@@ -21,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import re
 import sys
 import time
@@ -36,17 +46,17 @@ OPS_PER_UPDATE = 10
 # FP32 VALU lane-operations.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# On-chip gather bound: LDS delivers 128 bytes per clock per CU; an update
-# reads its four taps from LDS, 16 bytes as float32 or 8 bytes as two
-# binary16 pair words.
-LDS_BYTES_PER_CLK_CU = 128
-# Calibration copy for the HBM byte counters: a plain device-to-device copy of
-# this many bytes, run once when --calibrate-copy is given.
-CALIBRATION_BYTES = 1 << 30
+# Nominal LDS bandwidth: 128 bytes per clock per CU.
+LDS_NOMINAL_GBS = 256 * 128 * 2.4e9 / 1e9
+# LDS bytes an update reads: binary16 taps are one ds_read2_b32 of two pair
+# words (8 bytes), float32 taps two of them (16 bytes).
+TAP_BYTES = {"f16": 8, "f32": 16}
 # Measured HBM traffic of the back-projection kernel (FETCH_SIZE + WRITE_SIZE,
-# scaled by the calibration copy) and the hash of the sources it was taken on.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_kernel_c2_512cube_1024views_traffic.md")
+# scaled by a plain copy of known size) and the hash of the sources it was
+# taken on, per storage.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_kernel_c3_1024cube_2048views_traffic.md")
 KERNEL_SOURCES = ("bp.hip", "footprint.h", "internal.h", "geometry.cpp")
+TOL = {"f32": 1e-5, "f16": 1e-3}
 
 
 def kernel_source_hash() -> str:
@@ -57,10 +67,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the FP16 back-projection from the committed
-    counter summary, or None if it is missing, for another workload, or taken
-    on other kernel sources."""
+def measured_traffic(workload: str, storage: str):
+    """HBM bytes per launch of the back-projection for one storage from the
+    committed counter summary, or None if it is missing, for another
+    workload, or taken on other kernel sources."""
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
@@ -71,7 +81,7 @@ def measured_traffic(workload: str):
     if fields.get("workload") != workload:
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields["traffic_bytes_per_launch_" + storage])
     except (KeyError, ValueError):
         return None
 
@@ -80,38 +90,162 @@ def log(*a):
     print("[bench %s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(cfg, mats, seconds: float):
-    """The FP64 oracle on a centred sub-block of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def subblocks(shape, b=64):
+    """Eight b^3 boxes ((k0,k1),(j0,j1),(i0,i1)): the centre, four corners and
+    three edge midpoints of a [nz,ny,nx] volume."""
+    nz, ny, nx = shape
+
+    def at(n, where):
+        b_ = min(b, n)
+        return {"lo": 0, "mid": n // 2 - b_ // 2, "hi": n - b_}[where], b_
+
+    out = []
+    for kw, jw, iw in (("mid", "mid", "mid"), ("lo", "lo", "lo"), ("hi", "lo", "hi"),
+                       ("lo", "hi", "hi"), ("hi", "hi", "lo"), ("mid", "lo", "lo"),
+                       ("lo", "mid", "hi"), ("hi", "hi", "mid")):
+        (k0, bk), (j0, bj), (i0, bi) = at(nz, kw), at(ny, jw), at(nx, iw)
+        out.append(((k0, k0 + bk), (j0, j0 + bj), (i0, i0 + bi)))
+    return out
+
+
+def accuracy_and_oracle(cfg, mats, filt, h, sc, vol32, vol16):
+    """rel-L2 of the timed volumes (binary16 against float32 storage over the
+    whole volume; both against the FP64 oracle on eight 64^3 sub-blocks) and
+    the oracle's own throughput on those blocks (the CPU baseline)."""
     import numpy as np
+    import torch
     import oracle
-    import workloads as wl
-    nz, ny, nx = cfg["shape"]
+    from oracle import window as ow
+
+    shape, voxel = cfg["shape"], cfg["voxel"]
+    nz, ny, nx = shape
     npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
-    log("cpu baseline: host stack", (npv, nh, nw))
-    proj = wl.gaussian(cfg["seed"] + 999, (npv, nh, nw))
+    # whole volume, binary16 against float32 storage (slabs of 64 slices)
+    num = den = 0.0
+    for k0 in range(0, nz, 64):
+        a = vol16[k0:k0 + 64].double()
+        b = vol32[k0:k0 + 64].double()
+        num += float(((a - b) ** 2).sum())
+        den += float((b ** 2).sum())
+    f16_vs_f32 = (num / den) ** 0.5 if den > 0 else float("inf")
+    log("accuracy: f16 vs f32 storage (whole volume) %.3e" % f16_vs_f32)
+
     threads = oracle.max_threads()
-
-    def run(b):
-        k0, j0, i0 = nz // 2 - b // 2, ny // 2 - b // 2, nx // 2 - b // 2
+    sc_h = sc.cpu().numpy()
+    acc = dict(e32=0.0, r32=0.0, e16=0.0, e16d=0.0, r16=0.0)
+    t_oracle = 0.0
+    n_oracle = 0
+    single = None
+    for q, box in enumerate(subblocks(shape)):
+        (k0, k1), (j0, j1), (i0, i1) = box
+        origin, wr, wc = ow.block_windows(mats, shape, voxel, box)
+        w32 = ow.cut_windows_device(filt, origin, wr, wc)
+        w16 = ow.cut_windows_device(h, origin, wr, wc)
         t = time.perf_counter()
-        oracle.backproject_block(proj, mats, cfg["shape"], cfg["voxel"],
-                                 ((k0, k0 + b), (j0, j0 + b), (i0, i0 + b)))
-        return time.perf_counter() - t
+        ref32 = oracle.backproject_block(w32, mats, shape, voxel, box, origin=origin,
+                                         detector=(nh, nw))
+        ref16 = oracle.backproject_block(w16, mats, shape, voxel, box, scale=sc_h,
+                                         origin=origin, detector=(nh, nw))
+        t_oracle += time.perf_counter() - t
+        n_oracle += 2 * ref32.size * npv
+        g32 = vol32[k0:k1, j0:j1, i0:i1].double().cpu().numpy()
+        g16 = vol16[k0:k1, j0:j1, i0:i1].double().cpu().numpy()
+        acc["e32"] += float(((g32 - ref32) ** 2).sum())
+        acc["r32"] += float((ref32 ** 2).sum())
+        acc["e16"] += float(((g16 - ref32) ** 2).sum())
+        acc["e16d"] += float(((g16 - ref16) ** 2).sum())
+        acc["r16"] += float((ref16 ** 2).sum())
+        if q == 0:
+            # one thread, the first 128 views of the centre block
+            nv = min(128, npv)
+            t = time.perf_counter()
+            oracle.backproject_block(w32[:nv], mats[:nv], shape, voxel, box, origin=origin[:nv],
+                                     detector=(nh, nw), threads=1)
+            dt1 = time.perf_counter() - t
+            single = ref32.size * nv / dt1 / 1e9
+        log("accuracy: block %d %s window %dx%d" % (q, box, wr, wc))
+    rel = {
+        "f16_vs_f32_storage": f16_vs_f32,
+        "f32_vs_oracle": (acc["e32"] / acc["r32"]) ** 0.5,
+        "f16_vs_oracle": (acc["e16"] / acc["r32"]) ** 0.5,
+        "f16_vs_oracle_dequantised": (acc["e16d"] / acc["r16"]) ** 0.5,
+        "oracle_blocks": "eight 64^3 sub-blocks (centre, four corners, three edges), all %d views" % npv,
+    }
+    rel["ok"] = bool(rel["f32_vs_oracle"] <= TOL["f32"] and rel["f16_vs_oracle"] <= TOL["f16"]
+                     and rel["f16_vs_f32_storage"] <= TOL["f16"])
+    cpu = {"value": n_oracle / t_oracle / 1e9, "unit": "GUPS", "cores": threads, "kind": "oracle",
+           "sample": "FP64 oracle on the eight 64^3 sub-blocks of the accuracy check, %d views, "
+                     "both stacks (float32 and dequantised binary16), each view's detector "
+                     "window only; %.1f s" % (npv, t_oracle),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "single_core_gups": single,
+           "single_core_sample": "centre 64^3 block, first %d views, 1 thread" % min(128, npv)}
+    return rel, cpu
 
-    b = 8
-    dt = run(b)
-    while dt < 0.5 and b < 64:
-        b *= 2
-        dt = run(b)
-    rate = b ** 3 * npv / dt
-    b2 = int(round((seconds * rate / npv) ** (1.0 / 3.0)))
-    b2 = max(8, min(b2, min(nx, ny, nz)))
-    dt = run(b2)
-    gups = b2 ** 3 * npv / dt / 1e9
-    log("cpu baseline: %d^3 block x %d views in %.2fs, %d threads" % (b2, npv, dt, threads))
-    return {"value": gups, "unit": "GUPS", "cores": threads, "kind": "oracle",
-            "sample": "centred %d^3 sub-block of the %dx%dx%d volume, all %d views, "
-                      "Gaussian projections of the same shape; %.1f s" % (b2, nx, ny, nz, npv, dt)}
+
+def measure_peaks(buf, dev):
+    """Ceilings measured on this GPU (include/fdk_peaks.h): best of 5 launches
+    of an HBM stream read, LDS reads and a float32 FMA loop."""
+    import torch
+    from paper_2104_13248_amd import peaks as pk
+
+    stream = torch.cuda.current_stream(dev)
+    sink = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            work = fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            out.append(work / (a.elapsed_time(b) * 1e-3))
+        return max(out)
+
+    nbytes = min(buf.numel() * buf.element_size(), 16 << 30) // 16 * 16
+    res = {"hbm_read_gbs": best(lambda: pk.hbm_read(buf, nbytes, 256 * 16, sink)) / 1e9,
+           "hbm_read_bytes": nbytes}
+    for pat in ("b32", "read2_b32", "b64", "b128", "taps_f16", "taps_f32"):
+        res["lds_%s_gbs" % pat] = best(lambda: pk.lds_read(pat, 256 * 20, 1000, dev, sink)) / 1e9
+    res["valu_fma_tops"] = best(lambda: pk.valu_fma(256 * 16, 1000, dev, sink)) / 1e12
+    return res
+
+
+def h2d_inclusive(vol, h, sc, mats, voxel, dev):
+    """Secondary timing: back-projection including the host-to-device copy
+    of the binary16 stack from pinned host memory (the paper's GPU comparison
+    counts the upload of the projections, Section 4.5)."""
+    import torch
+    import paper_2104_13248_amd as fdk
+    host = torch.empty(h.shape, dtype=h.dtype, pin_memory=True)
+    host.copy_(h)
+    dst = torch.empty_like(h)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(2):
+        vol.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        dst.copy_(host, non_blocking=True)
+        fdk.backproject(vol, dst, mats, voxel, scale=sc)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    del host, dst
+    return min(times)
 
 
 # Dense FP32 matrix-core peak of MI355X (v_mfma_f32_* instructions).
@@ -299,9 +433,14 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c2")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="oracle seconds per operation of --ops")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the accuracy check and the CPU baseline (profiling runs)")
+    ap.add_argument("--no-h2d", action="store_true", help="skip the upload-inclusive timing")
+    ap.add_argument("--only", choices=("f16", "f32"), default=None,
+                    help="time one storage only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy (reference for byte counters)")
     ap.add_argument("--ops", action="store_true",
@@ -327,83 +466,146 @@ def main() -> int:
     nz, ny, nx = cfg["shape"]
     npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
     scan = cfg["scan"]
-    mats = fdk.scan_matrices(scan, npv, nh, nw)
-    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], npv, nh, nw, mats, f16=True)   # the FP16 step's launch
-    log("config", args.config, cfg["shape"], (npv, nh, nw), "plan", plan)
+    mats = np.asarray(fdk.scan_matrices(scan, npv, nh, nw))
+    plans = {st: fdk.bp_plan(cfg["shape"], cfg["voxel"], npv, nh, nw, mats, f16=(st == "f16"))
+             for st in ("f16", "f32")}
+    log("config", args.config, cfg["shape"], (npv, nh, nw), "plans", plans)
+    stream = torch.cuda.current_stream(dev)
 
-    # ---- synthetic input, generated on the GPU (not timed)
+    # ---- synthetic input, generated on the GPU (not timed): one phantom,
+    # line integrals, FDK filter into float32 and into binary16 + scale
     ell = wl.config_ellipsoids(cfg, 0)
     filt = torch.empty((npv, nh, nw), dtype=torch.float32, device=dev)
-    chunk = 128
+    h = torch.empty((npv, nh, nw), dtype=torch.float16, device=dev)
+    sc = torch.empty(npv, dtype=torch.float32, device=dev)
+    chunk = 64
     raw = torch.empty((chunk, nh, nw), dtype=torch.float32, device=dev)
     for v0 in range(0, npv, chunk):
         n = min(chunk, npv - v0)
         raw[:n].zero_()
         fdk.phantom_project(ell, scan, raw[:n], view_begin=v0, np_total=npv)
         fdk.fdk_filter(raw[:n], scan, np_total=npv, out=filt[v0:v0 + n])
+        fdk.fdk_filter(raw[:n], scan, np_total=npv, out=h[v0:v0 + n], dtype=torch.float16,
+                       scale=sc[v0:v0 + n])
+    torch.cuda.synchronize()
+    log("input ready: %d ellipsoids, float32 stack %.2f GiB, binary16 stack %.2f GiB"
+        % (len(ell), filt.numel() * 4 / 2**30, h.numel() * 2 / 2**30))
+
+    # filter and stand-alone FP16 pre-pass cost (context: not in the step)
+    n = min(chunk, npv)
+    tmp32 = torch.empty_like(raw[:n])
+    tmp16 = torch.empty(raw[:n].shape, dtype=torch.float16, device=dev)
+    tmps = torch.empty(n, dtype=torch.float32, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(stream)
+    fdk.fdk_filter(raw[:n], scan, np_total=npv, out=tmp32)
+    ev[1].record(stream)
+    fdk.fdk_filter(raw[:n], scan, np_total=npv, out=tmp16, dtype=torch.float16, scale=tmps)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    del tmp32, tmp16, tmps
+    filter_ms = {"f32_per_view": ev[0].elapsed_time(ev[1]) / n,
+                 "f16_per_view": ev[1].elapsed_time(ev[2]) / n}
     del raw
     torch.cuda.synchronize()
-    log("input ready: filtered stack %.2f GiB" % (filt.numel() * 4 / 2**30))
+    ev[0].record(stream)
+    hq, sq = fdk.quantize_f16(filt)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    prepass_ms = ev[0].elapsed_time(ev[1])
+    same = bool(torch.equal(hq.view(torch.int16), h.view(torch.int16)) and torch.equal(sq, sc))
+    del hq, sq
+    log("filter ms/view f32 %.3f f16 %.3f; stand-alone pre-pass %.2f ms; filter f16 output "
+        "bit-equal to the pre-pass: %s" % (filter_ms["f32_per_view"], filter_ms["f16_per_view"],
+                                           prepass_ms, same))
 
     if args.calibrate_copy:
-        src = torch.ones(CALIBRATION_BYTES // 4, dtype=torch.float32, device=dev)
+        src = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        log("calibration copy: %d bytes" % CALIBRATION_BYTES)
+        log("calibration copy: %d bytes" % (1 << 30))
 
-    vol = torch.zeros(cfg["shape"], dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
+    vols = {st: torch.zeros(cfg["shape"], dtype=torch.float32, device=dev) for st in ("f16", "f32")}
     n_upd = nx * ny * nz * npv
 
-    def step_f16(events=None):
-        vol.zero_()
-        h, s = fdk.quantize_f16(filt)
-        if events is not None:
-            events[0].record(stream)
-        fdk.backproject(vol, h, mats, cfg["voxel"], scale=s)
-        if events is not None:
-            events[1].record(stream)
-
-    def step_f32(events=None):
+    def step(st, events=None):
+        vol = vols[st]
         vol.zero_()
         if events is not None:
             events[0].record(stream)
-        fdk.backproject(vol, filt, mats, cfg["voxel"])
+        if st == "f16":
+            fdk.backproject(vol, h, mats, cfg["voxel"], scale=sc)
+        else:
+            fdk.backproject(vol, filt, mats, cfg["voxel"])
         if events is not None:
             events[1].record(stream)
 
     results = {}
-    for name, step in (("f32", step_f32), ("f16", step_f16)):
+    for st in (("f32", "f16") if args.only is None else (args.only,)):
         for _ in range(args.warmup):
-            step()
+            step(st)
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for q in range(args.steps):
-            step(ev[q])
+            step(st, evs[q])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
         ms = (t1 - t0) * 1e3 / args.steps
-        results[name] = dict(ms_per_step=ms, kernel_ms=k_ms, gups=n_upd / (ms * 1e-3) / 1e9,
-                             kernel_gups=n_upd / (k_ms * 1e-3) / 1e9)
-        log(name, results[name])
-        print("progress: %s timed" % name, file=sys.stderr, flush=True)
+        results[st] = dict(ms_per_step=ms, kernel_ms=k_ms, gups=n_upd / (ms * 1e-3) / 1e9,
+                           kernel_gups=n_upd / (k_ms * 1e-3) / 1e9)
+        log(st, results[st])
+        print("progress: %s timed" % st, file=sys.stderr, flush=True)
+    if args.only is not None:
+        print(json.dumps({"storage": args.only, **results[args.only]}), flush=True)
+        return 0
 
-    f16 = results["f16"]
-    f32 = results["f32"]
-    k_s = f16["kernel_ms"] * 1e-3
-    achieved = n_upd * OPS_PER_UPDATE / k_s / 1e12
-    vol_bytes = nx * ny * nz * 4
-    hbm_alg = 2 * vol_bytes + npv * nh * nw * 2 + npv * 4           # volume RMW + f16 stack
-    lds_bound = 256 * 2.4e9 * LDS_BYTES_PER_CLK_CU / 8 / 1e9      # FP16 storage: 8 B/update
+    peaks = measure_peaks(filt, dev)
+    log("peaks", peaks)
     workload = "fdk_backprojection_%dx%dx%d_%dviews_%dx%d" % (nx, ny, nz, npv, nh, nw)
-    traffic = measured_traffic(workload)
+    vol_bytes = nx * ny * nz * 4
+
+    def roofline(st):
+        r = results[st]
+        k_s = r["kernel_ms"] * 1e-3
+        ops = n_upd * OPS_PER_UPDATE / k_s / 1e12
+        hbm_alg = 2 * vol_bytes + npv * nh * nw * (2 if st == "f16" else 4) + \
+            (npv * 4 if st == "f16" else 0)
+        lds_gbs = n_upd * TAP_BYTES[st] / k_s / 1e9
+        lds_peak = peaks["lds_read2_b32_gbs"]
+        hbm_gbs = hbm_alg / k_s / 1e9
+        mem_bound_gups = min(lds_peak * 1e9 / TAP_BYTES[st],
+                             peaks["hbm_read_gbs"] * 1e9 / (hbm_alg / n_upd)) / 1e9
+        valu_bound_gups = peaks["valu_fma_tops"] * 1e12 / OPS_PER_UPDATE / 1e9
+        return {"bound": "alu", "achieved": ops, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": ops / VALU_PEAK_TOPS, "traffic": measured_traffic(workload, st),
+                "traffic_unit": "bytes/launch",
+                "kernel": "bp_kernel<%d,%d,%s>" % (plans[st]["kz"], plans[st]["lds_pitch"],
+                                                   "true" if st == "f16" else "false"),
+                "kernel_ms": r["kernel_ms"], "ops_per_update": OPS_PER_UPDATE,
+                "measured_peak": peaks["valu_fma_tops"],
+                "frac_of_measured": ops / peaks["valu_fma_tops"],
+                "memory_roofline": {
+                    "bound": "lds_gather", "tap_bytes_per_update": TAP_BYTES[st],
+                    "achieved_gbs": lds_gbs, "peak_gbs": lds_peak,
+                    "peak_source": "measured ds_read2_b32, no bank conflict",
+                    "frac": lds_gbs / lds_peak, "nominal_peak_gbs": LDS_NOMINAL_GBS,
+                    "tap_pattern_gbs": peaks["lds_taps_%s_gbs" % st],
+                    "hbm_algorithmic_bytes": hbm_alg, "hbm_achieved_gbs": hbm_gbs,
+                    "hbm_peak_gbs": peaks["hbm_read_gbs"],
+                    "hbm_frac": hbm_gbs / peaks["hbm_read_gbs"],
+                    "bound_gups": mem_bound_gups,
+                    "frac_of_bound": r["kernel_gups"] / mem_bound_gups},
+                "valu_bound_gups": valu_bound_gups,
+                "binding_ceiling": "valu" if valu_bound_gups < mem_bound_gups else "memory"}
+
+    f16, f32 = results["f16"], results["f32"]
     out = {
         "metric": "GUPS (giga voxel-updates/s) FDK backproject, FP16-store vs FP32 at rel-L2<=1e-3",
         "value": f16["gups"],
@@ -416,31 +618,40 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic: GPU analytic line integrals of a seeded 40-ellipsoid phantom, "
-                "FDK ramp-filtered; FP16 storage with per-view scale",
+        "data": "synthetic: GPU analytic line integrals of a seeded %d-ellipsoid phantom, "
+                "FDK ramp-filtered; binary16 storage with per-view scale written by the "
+                "filter" % len(ell),
         "config": {"workload": workload,
                    "volume": [nz, ny, nx], "voxel_mm": list(cfg["voxel"]), "views": npv,
                    "detector": [nh, nw], "pixel_mm": [scan["du"], scan["dv"]],
                    "sod_mm": scan["sod"], "sdd_mm": scan["sdd"], "storage": "f16",
-                   "tile": [plan["tile_x"], plan["tile_y"], plan["kz"]],
-                   "lds_bytes": plan["lds_bytes"]},
+                   "tile": [plans["f16"]["tile_x"], plans["f16"]["tile_y"], plans["f16"]["kz"]],
+                   "lds_bytes": plans["f16"]["lds_bytes"]},
         "fp32_storage": {"value": f32["gups"], "unit": "GUPS", "ms_per_step": f32["ms_per_step"],
-                         "kernel_ms": f32["kernel_ms"]},
+                         "kernel_ms": f32["kernel_ms"], "roofline": roofline("f32")},
         "f16_over_f32": f16["gups"] / f32["gups"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                     "traffic_unit": "bytes/launch", "kernel": "bp_kernel", "kernel_ms": f16["kernel_ms"],
-                     "ops_per_update": OPS_PER_UPDATE,
-                     "hbm_algorithmic_bytes": hbm_alg,
-                     "hbm_algorithmic_gbs": hbm_alg / k_s / 1e9,
-                     "hbm_frac": hbm_alg / k_s / 1e9 / HBM_PEAK_GBS,
-                     "lds_gather_bound_gups": lds_bound,
-                     "lds_gather_frac": f16["kernel_gups"] / lds_bound},
+        "roofline": roofline("f16"),
+        "peaks_measured": peaks,
+        "filter_ms": filter_ms,
+        "f16_prepass_ms": prepass_ms,
+        "filter_f16_equals_prepass": same,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, np.asarray(mats), args.cpu_seconds)
+    if not args.no_h2d:
+        t = h2d_inclusive(vols["f16"], h, sc, mats, cfg["voxel"], dev)
+        out["h2d_inclusive"] = {"value": n_upd / t / 1e9, "unit": "GUPS", "s": t,
+                                "what": "binary16 stack uploaded from pinned host memory, "
+                                        "then back-projected (one call)"}
+        log("h2d inclusive %.3f s" % t)
+        step("f16")                     # the checked volume is a timed-step result
+        torch.cuda.synchronize()
+    rc = 0
+    if not args.no_check:
+        rel, cpu = accuracy_and_oracle(cfg, mats, filt, h, sc, vols["f32"], vols["f16"])
+        out["rel_l2"] = rel
+        out["cpu_baseline"] = cpu
+        rc = 0 if rel["ok"] else 3
     print(json.dumps(out), flush=True)
-    return 0
+    return rc
 
 
 if __name__ == "__main__":

@@ -133,17 +133,30 @@ fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
  *
  *   q = raw * sdd / sqrt(sdd^2 + u_mm^2 + v_mm^2)           cosine weight
  *   q = tau * (h * q)   along each detector row              Ram-Lak ramp
- *   out = q * arc / (2 np_total)                              angular weight
+ *   p = q * arc / (2 np_total)                                angular weight
  *
  * with u_mm = (c - (nw-1)/2 - u_off) du, v_mm = (r - (nh-1)/2 - v_off) dv,
  * tau = du sod / sdd, h[0] = 1/(4 tau^2), h[n odd] = -1/(pi^2 n^2 tau^2),
  * h[n even, != 0] = 0, and a linear (zero-padded) convolution over the row.
- * raw, out: device float32 [np][nh][nw] (may not overlap).  sg->dtype must be
- * FDK_F32.  Back-projecting `out` with the matrices of the same scan (weight
- * 1/w^2, w = 1 at the isocentre) gives the FDK reconstruction.
+ *
+ * raw        device float32 [np][nh][nw]; sg->dtype must be FDK_F32.
+ * out_dtype  FDK_F32: out is device float32 [np][nh][nw] and receives p;
+ *            out_scale must be NULL.
+ *            FDK_F16: out is device uint16 [np][nh][nw] and receives the
+ *            binary16 storage of p with the rule of fdk_quantize_f16 (per-view
+ *            power-of-two scale from max |p_s|, round to nearest even), bit
+ *            for bit what fdk_quantize_f16 makes of the FDK_F32 output;
+ *            out_scale is device float32 [np] and receives the scales.  The
+ *            per-view maxima are taken as the filter writes its output (a few
+ *            views at a time through a stream-ordered float32 workspace of at
+ *            most 64 MiB, or one view if a view is larger), so no separate
+ *            pass over a float32 stack is needed.
+ * raw and out may not overlap.  Back-projecting the result with the matrices
+ * of the same scan (weight 1/w^2, w = 1 at the isocentre) gives the FDK
+ * reconstruction.
  */
-fdk_status fdk_filter(const fdk_stack* sg, const float* raw, float* out,
-                      double du, double dv, double sod, double sdd,
+fdk_status fdk_filter(const fdk_stack* sg, const float* raw, int32_t out_dtype, void* out,
+                      float* out_scale, double du, double dv, double sod, double sdd,
                       double u_off, double v_off, double arc, int32_t np_total,
                       void* stream);
 

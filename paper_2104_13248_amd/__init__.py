@@ -66,6 +66,9 @@ def backproject_slab(vol_slab: torch.Tensor, shape, k_begin: int, proj: torch.Te
         if scale is None:
             raise ValueError("float16 projections need a per-view scale")
         s = _dev_ptr(scale, "scale", (torch.float32,), dev)
+        if tuple(scale.shape) != (proj.shape[0],):
+            raise ValueError("scale must have shape [%d] (one per view), got %s"
+                             % (proj.shape[0], tuple(scale.shape)))
     elif scale is not None:
         raise ValueError("scale is only accepted with float16 projections")
     npv, nh, nw = proj.shape
@@ -96,20 +99,41 @@ def forwardproject(vol: torch.Tensor, proj: torch.Tensor, mats, voxel,
 
 
 def fdk_filter(raw: torch.Tensor, scan: dict, np_total: int | None = None,
-               out: torch.Tensor | None = None) -> torch.Tensor:
-    """Cosine weight + Ram-Lak ramp + angular weight of raw line integrals."""
+               out: torch.Tensor | None = None, dtype=torch.float32,
+               scale: torch.Tensor | None = None):
+    """Cosine weight + Ram-Lak ramp + angular weight of raw line integrals.
+
+    dtype float32: returns the filtered stack (``out`` if given).
+    dtype float16: returns (binary16 stack, float32 per-view scale), the FP16
+    storage rule applied by the filter itself (``out`` / ``scale`` if given)."""
     dev = raw.device
     r = _dev_ptr(raw, "raw", (torch.float32,))
-    if out is None:
-        out = torch.empty_like(raw)
-    o = _dev_ptr(out, "out", (torch.float32,), dev)
     npv, nh, nw = raw.shape
+    if dtype == torch.float32:
+        if scale is not None:
+            raise ValueError("scale is only written with float16 output")
+        if out is None:
+            out = torch.empty_like(raw)
+        code, sp = FDK_F32, None
+    elif dtype == torch.float16:
+        if out is None:
+            out = torch.empty(raw.shape, dtype=torch.float16, device=dev)
+        if scale is None:
+            scale = torch.empty(npv, dtype=torch.float32, device=dev)
+        if tuple(scale.shape) != (npv,):
+            raise ValueError("scale must have shape [%d], got %s" % (npv, tuple(scale.shape)))
+        code, sp = FDK_F16, _dev_ptr(scale, "scale", (torch.float32,), dev)
+    else:
+        raise TypeError("dtype must be torch.float32 or torch.float16")
+    o = _dev_ptr(out, "out", (dtype,), dev)
+    if tuple(out.shape) != tuple(raw.shape):
+        raise ValueError("out must have the shape of raw")
     sg = stack_struct(npv, nh, nw)
     with torch.cuda.device(dev):
-        check(lib.fdk_filter(sg, r, o, scan["du"], scan["dv"], scan["sod"], scan["sdd"],
+        check(lib.fdk_filter(sg, r, code, o, sp, scan["du"], scan["dv"], scan["sod"], scan["sdd"],
                              scan["u_off"], scan["v_off"], scan["arc"],
                              int(np_total if np_total is not None else npv), _stream(dev)))
-    return out
+    return out if dtype == torch.float32 else (out, scale)
 
 
 def quantize_f16(proj: torch.Tensor):

@@ -55,7 +55,7 @@ def _load():
         "fdk_backproject": [VP, P, SP, P, P, P, P],
         "fdk_backproject_slab": [VP, I, I, P, SP, P, P, P, P],
         "fdk_forwardproject": [VP, P, SP, P, P, P],
-        "fdk_filter": [SP, P, P, D, D, D, D, D, D, D, I, P],
+        "fdk_filter": [SP, P, I, P, P, D, D, D, D, D, D, D, I, P],
         "fdk_quantize_f16": [I, I, I, P, P, P, P],
         "fdk_circular_matrices": [I, D, D, D, D, I, I, D, D, D, D, P],
         "fdk_phantom_project": [P, I, SP, P, D, D, D, D, D, D, D, D, I, I, P],
@@ -69,6 +69,10 @@ def _load():
         "fdk_adam": [I, P, P, P, P, F, F, F, F, I, P],
         # include/fdk_ablation.h
         "fdk_backproject_variant": [I, I, VP, P, SP, P, P, P],
+        # include/fdk_peaks.h
+        "fdk_peak_hbm_read": [P, ctypes.c_int64, I, P, P],
+        "fdk_peak_lds_read": [I, I, I, P, P, P],
+        "fdk_peak_valu_fma": [I, I, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -89,7 +93,8 @@ EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_forwardproject", "fdk
            "fdk_last_error", "fdk_status_string",
            "fdk_cosine_weight", "fdk_conv1d_forward", "fdk_conv1d_backward_data",
            "fdk_conv1d_backward_weight", "fdk_sqerr", "fdk_adam",
-           "fdk_backproject_variant")
+           "fdk_backproject_variant",
+           "fdk_peak_hbm_read", "fdk_peak_lds_read", "fdk_peak_valu_fma")
 
 
 def check(code: int) -> None:

@@ -167,14 +167,21 @@ extern "C" fdk_status fdk_forwardproject(const fdk_volume* vg, const float* vol,
     return s != FDK_OK ? s : s2;
 }
 
-extern "C" fdk_status fdk_filter(const fdk_stack* sg, const float* raw, float* out, double du,
-                                 double dv, double sod, double sdd, double u_off, double v_off,
-                                 double arc, int32_t np_total, void* stream)
+extern "C" fdk_status fdk_filter(const fdk_stack* sg, const float* raw, int32_t out_dtype,
+                                 void* out, float* out_scale, double du, double dv, double sod,
+                                 double sdd, double u_off, double v_off, double arc,
+                                 int32_t np_total, void* stream)
 {
     fdk_status s = validate_stack(sg, false);
     if (s != FDK_OK) return s;
     if (!raw || !out) return fail(FDK_E_INVALID, "raw/out pointer is NULL");
-    if (raw == out) return fail(FDK_E_INVALID, "raw and out must not overlap");
+    if (out_dtype != FDK_F32 && out_dtype != FDK_F16)
+        return fail(FDK_E_INVALID, "out_dtype must be FDK_F32 or FDK_F16");
+    if (out_dtype == FDK_F16 && !out_scale)
+        return fail(FDK_E_INVALID, "binary16 output needs a per-view scale array");
+    if (out_dtype == FDK_F32 && out_scale)
+        return fail(FDK_E_INVALID, "a scale array is only written with binary16 output");
+    if ((const void*)raw == out) return fail(FDK_E_INVALID, "raw and out must not overlap");
     if (!(du > 0) || !(dv > 0) || !(sod > 0) || !(sdd > 0) || !std::isfinite(du) ||
         !std::isfinite(dv) || !std::isfinite(sod) || !std::isfinite(sdd) ||
         !std::isfinite(u_off) || !std::isfinite(v_off) || !std::isfinite(arc))
@@ -183,7 +190,9 @@ extern "C" fdk_status fdk_filter(const fdk_stack* sg, const float* raw, float* o
     if (sg->nw > 65536) return fail(FDK_E_UNSUPPORTED, "rows longer than 65536 pixels");
     FilterLaunch a;
     a.raw = raw;
-    a.out = out;
+    a.out = out_dtype == FDK_F32 ? (float*)out : nullptr;
+    a.out16 = out_dtype == FDK_F16 ? (uint16_t*)out : nullptr;
+    a.scale = out_scale;
     a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
     a.du = du; a.dv = dv; a.sod = sod; a.sdd = sdd; a.u_off = u_off; a.v_off = v_off;
     a.arc = arc;
@@ -282,6 +291,8 @@ extern "C" fdk_status fdk_cosine_weight(const fdk_stack* sg, const float* raw, f
     FilterLaunch a;
     a.raw = raw;
     a.out = out;
+    a.out16 = nullptr;
+    a.scale = nullptr;
     a.np = sg->np; a.nh = sg->nh; a.nw = sg->nw;
     a.du = du; a.dv = dv; a.sod = sdd; a.sdd = sdd; a.u_off = u_off; a.v_off = v_off;
     a.arc = 1.0;

@@ -39,7 +39,24 @@ struct FilterArgs {
     float cu, cv, du, dv, sdd2, sdd;
     float h0;          // h[0] * tau * angular weight
     float hscale;      // -1/(pi^2 tau^2) * tau * angular weight
+    unsigned* maxbits; // per-view |out| maxima (float bits, atomicMax) or nullptr
 };
+
+// Maximum over the block of a non-negative per-thread value, posted with one
+// atomicMax to the bit pattern of maxbits[view] (bit order = value order for
+// non-negative floats, so the result does not depend on the order).  `part`
+// holds one word per wave.  Every thread of the block must call it.
+__device__ __forceinline__ void post_block_max(float m, float* part, unsigned* maxbits, int64_t view)
+{
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    const int nwaves = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nwaves; ++w) m = fmaxf(m, part[w]);
+        atomicMax(&maxbits[view], __float_as_uint(m));
+    }
+}
 
 __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const FilterArgs A)
 {
@@ -62,6 +79,7 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const FilterArgs
         hodd[m] = A.hscale / (n * n);
     }
     __syncthreads();
+    float mx = 0.f;
     for (int c = threadIdx.x; c < A.nw; c += kFilterThreads) {
         // taps c - n and c + n for odd n; both sides while both exist
         const int both = min(c, A.nw - 1 - c);
@@ -73,7 +91,13 @@ __global__ __launch_bounds__(kFilterThreads) void filter_kernel(const FilterArgs
         } else {
             for (; 2 * m + 1 <= c; ++m) acc = fmaf(hodd[m], q[c - 2 * m - 1], acc);
         }
-        dst[c] = fmaf(A.h0, q[c], acc);
+        const float y = fmaf(A.h0, q[c], acc);
+        dst[c] = y;
+        mx = fmaxf(mx, fabsf(y));
+    }
+    if (A.maxbits) {
+        __shared__ float part[kFilterThreads / 64];
+        post_block_max(mx, part, A.maxbits, row / A.nh);
     }
 }
 
@@ -267,13 +291,28 @@ __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const Filt
         return make_float2(z.x * h, -z.y * h);
     };
     float* d0 = A.out + row0 * A.nw;
+    float m0 = 0.f, m1 = 0.f;                     // |output| maxima of the two rows
     auto to_rows = [&](int c, float2 y) {
         if (c < A.nw) {
             d0[c] = y.x;
-            if (two) d0[A.nw + c] = -y.y;
+            m0 = fmaxf(m0, fabsf(y.x));
+            if (two) {
+                d0[A.nw + c] = -y.y;
+                m1 = fmaxf(m1, fabsf(y.y));
+            }
         }
     };
     fft_passes<M, T, 1, true, false>(buf, tw, tid, conj_zh, to_rows);
+    if (A.maxbits) {
+        __shared__ float part[2][4];
+        const int64_t s0v = row0 / A.nh, s1v = (row0 + 1) / A.nh;
+        if (!two || s0v == s1v) {
+            post_block_max(fmaxf(m0, m1), part[0], A.maxbits, s0v);
+        } else {
+            post_block_max(m0, part[0], A.maxbits, s0v);
+            post_block_max(m1, part[1], A.maxbits, s1v);
+        }
+    }
 }
 
 // tw[e] = exp(-2 pi i e / M); H[k] = (1/M) (h0 + 2 sum_{odd n < nw} hs / n^2
@@ -331,6 +370,7 @@ FilterArgs filter_args(const FilterLaunch& a)
     A.sdd2 = (float)(a.sdd * a.sdd);
     A.h0 = (float)(1.0 / (4.0 * tau * tau) * tau * wang);
     A.hscale = (float)(-1.0 / (pi * pi * tau * tau) * tau * wang);
+    A.maxbits = nullptr;
     return A;
 }
 
@@ -347,42 +387,27 @@ fdk_status launch_cosine_weight(const FilterLaunch& a, void* stream)
     return check_launch("cosine-weight kernel");
 }
 
-fdk_status launch_filter(const FilterLaunch& a, void* stream)
+namespace {
+
+// Filter the rows of A (A.raw, A.out already offset to the first view):
+// nviews views of a.nh rows.  tw/H: the Fourier tables (nullptr for rows
+// longer than kFftMaxRow).
+fdk_status filter_rows(const FilterArgs& A, int32_t nviews, int32_t nh, int32_t nw, int M,
+                       const float* H, const float2* tw, hipStream_t st)
 {
-    const FilterArgs A = filter_args(a);
-    const int64_t rows = (int64_t)a.np * a.nh;
-    hipStream_t st = (hipStream_t)stream;
-    if (a.nw <= kFftMaxRow) {
-        int M = 16;
-        while (M < 2 * a.nw - 1) M *= 2;
-        if ((rows + 1) / 2 >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "too many detector rows");
-        void* tab = nullptr;
-        fdk_status s = device_alloc_async((size_t)M * (sizeof(float) + sizeof(float2)), st, &tab);
-        if (s != FDK_OK) return s;
-        float2* tw = (float2*)tab;
-        float* H = (float*)(tw + M);
-        const double tau = a.du * a.sod / a.sdd;
-        const double wang = a.arc / (2.0 * (double)a.np_total);
-        const double pi = 3.14159265358979323846;
-        hipLaunchKernelGGL(filter_tables_kernel, dim3(M), dim3(64), 0, st, M, a.nw,
-                           1.0 / (4.0 * tau * tau) * tau * wang, -1.0 / (pi * pi * tau * tau) * tau * wang,
-                           tw, H);
-        s = check_launch("filter table kernel");
-        if (s == FDK_OK) {
-            const dim3 g((unsigned)((rows + 1) / 2));
-            switch (M) {
-#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, dim3(fft_threads<m>()), 0, st, A, (const float*)H, (const float2*)tw, rows); break;
-                FDK_FFT(16) FDK_FFT(32) FDK_FFT(64) FDK_FFT(128) FDK_FFT(256) FDK_FFT(512)
-                FDK_FFT(1024) FDK_FFT(2048) FDK_FFT(4096)
+    const int64_t rows = (int64_t)nviews * nh;
+    if (nw <= kFftMaxRow) {
+        const dim3 g((unsigned)((rows + 1) / 2));
+        switch (M) {
+#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, dim3(fft_threads<m>()), 0, st, A, H, tw, rows); break;
+            FDK_FFT(16) FDK_FFT(32) FDK_FFT(64) FDK_FFT(128) FDK_FFT(256) FDK_FFT(512)
+            FDK_FFT(1024) FDK_FFT(2048) FDK_FFT(4096)
 #undef FDK_FFT
-            }
-            s = check_launch("filter kernel");
+            default: return fail(FDK_E_UNSUPPORTED, "no Fourier filter for this row length");
         }
-        const fdk_status s2 = device_free_async(tab, st);
-        return s != FDK_OK ? s : s2;
+        return check_launch("filter kernel");
     }
-    if (rows >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "too many detector rows");
-    const size_t lds = (size_t)(a.nw + (a.nw + 1) / 2 + 1) * sizeof(float);
+    const size_t lds = (size_t)(nw + (nw + 1) / 2 + 1) * sizeof(float);
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute((const void*)filter_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds) != hipSuccess)
@@ -390,6 +415,75 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
     }
     hipLaunchKernelGGL(filter_kernel, dim3((unsigned)rows), dim3(kFilterThreads), lds, st, A);
     return check_launch("filter kernel");
+}
+
+// Bytes of float32 workspace per chunk of views of the binary16 output: small
+// enough to stay in the last-level cache between the filter and the
+// conversion that reads it back.
+constexpr int64_t kF16ChunkBytes = 64ll << 20;
+
+}  // namespace
+
+fdk_status launch_filter(const FilterLaunch& a, void* stream)
+{
+    FilterArgs A = filter_args(a);
+    const int64_t rows = (int64_t)a.np * a.nh;
+    hipStream_t st = (hipStream_t)stream;
+    const bool fft = a.nw <= kFftMaxRow;
+    if (fft ? (rows + 1) / 2 >= (1ll << 31) : rows >= (1ll << 31))
+        return fail(FDK_E_UNSUPPORTED, "too many detector rows");
+    int M = 0;
+    void* tab = nullptr;
+    float2* tw = nullptr;
+    float* H = nullptr;
+    fdk_status s = FDK_OK;
+    if (fft) {
+        M = 16;
+        while (M < 2 * a.nw - 1) M *= 2;
+        s = device_alloc_async((size_t)M * (sizeof(float) + sizeof(float2)), st, &tab);
+        if (s != FDK_OK) return s;
+        tw = (float2*)tab;
+        H = (float*)(tw + M);
+        const double tau = a.du * a.sod / a.sdd;
+        const double wang = a.arc / (2.0 * (double)a.np_total);
+        const double pi = 3.14159265358979323846;
+        hipLaunchKernelGGL(filter_tables_kernel, dim3(M), dim3(64), 0, st, M, a.nw,
+                           1.0 / (4.0 * tau * tau) * tau * wang, -1.0 / (pi * pi * tau * tau) * tau * wang,
+                           tw, H);
+        s = check_launch("filter table kernel");
+    }
+    if (s == FDK_OK && !a.out16) {
+        s = filter_rows(A, a.np, a.nh, a.nw, M, H, tw, st);
+    } else if (s == FDK_OK) {
+        // binary16 output: chunks of views through a float32 workspace, the
+        // per-view maxima taken by the filter's epilogue
+        const int64_t npix = (int64_t)a.nh * a.nw;
+        int64_t chunk = kF16ChunkBytes / (npix * (int64_t)sizeof(float));
+        if (chunk < 1) chunk = 1;
+        if (chunk > a.np) chunk = a.np;
+        void* ws = nullptr;
+        void* mx = nullptr;
+        s = device_alloc_async((size_t)(chunk * npix) * sizeof(float), st, &ws);
+        if (s == FDK_OK) s = device_alloc_async((size_t)a.np * sizeof(unsigned), st, &mx);
+        if (s == FDK_OK) s = launch_clear_u32((unsigned*)mx, a.np, stream);
+        for (int64_t v0 = 0; s == FDK_OK && v0 < a.np; v0 += chunk) {
+            const int32_t nv = (int32_t)(v0 + chunk <= a.np ? chunk : a.np - v0);
+            FilterArgs C = A;
+            C.raw = a.raw + v0 * npix;
+            C.out = (float*)ws;
+            C.maxbits = (unsigned*)mx + v0;
+            s = filter_rows(C, nv, a.nh, a.nw, M, H, tw, st);
+            if (s == FDK_OK)
+                s = launch_quantize_with_max(nv, npix, (const float*)ws, (const unsigned*)mx + v0,
+                                             a.out16 + v0 * npix, a.scale + v0, stream);
+        }
+        for (void* d : {mx, ws}) {
+            const fdk_status e = device_free_async(d, st);
+            if (s == FDK_OK) s = e;
+        }
+    }
+    const fdk_status s2 = device_free_async(tab, st);
+    return s != FDK_OK ? s : s2;
 }
 
 }  // namespace fdk

@@ -131,11 +131,17 @@ fdk_status launch_forwardproject(const FpLaunch& a, const FpPlan& plan, void* st
 
 struct FilterLaunch {
     const float* raw;
-    float* out;
+    float* out;              // float32 output (out16 == nullptr)
+    uint16_t* out16;         // binary16 output, or nullptr
+    float* scale;            // [np] per-view scale of the binary16 output
     int32_t np, nh, nw;
     double du, dv, sod, sdd, u_off, v_off, arc;
     int32_t np_total;
 };
+// FDK filter into float32 `out`, or (out16 != nullptr) into binary16 codes
+// with one power-of-two scale per view (the rule of launch_quantize_f16):
+// views are filtered a few at a time into a stream-ordered float32 workspace
+// while their maxima are taken in the filter's epilogue, then converted.
 fdk_status launch_filter(const FilterLaunch& a, void* stream);
 // Cosine weight only (step 1 of the filter); uses raw, out, np, nh, nw, du,
 // dv, sdd, u_off, v_off of `a`.
@@ -164,6 +170,13 @@ fdk_status launch_adam(int n, float* p, const float* g, float* m, float* v, floa
 
 fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16_t* out,
                                float* scale, void* stream);
+// Pieces of the FP16 rule for producers that take the per-view maxima
+// themselves: zero `n` words (a fill kernel), and convert np views of npix
+// float32 values given the bit patterns of their absolute maxima.
+fdk_status launch_clear_u32(unsigned* p, int32_t n, void* stream);
+fdk_status launch_quantize_with_max(int32_t np, int64_t npix, const float* in,
+                                    const unsigned* maxbits, uint16_t* out, float* scale,
+                                    void* stream);
 
 struct PhantomLaunch {
     const double* ell;       // device [n_ell][16]

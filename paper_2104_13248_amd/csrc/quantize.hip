@@ -110,6 +110,26 @@ __global__ __launch_bounds__(kQThreads) void quantize_kernel(const float* __rest
 
 }  // namespace
 
+fdk_status launch_clear_u32(unsigned* p, int32_t n, void* stream)
+{
+    if (n <= 0) return FDK_OK;
+    hipLaunchKernelGGL(clear_u32, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, p, n);
+    return check_launch("clear kernel");
+}
+
+fdk_status launch_quantize_with_max(int32_t np, int64_t npix, const float* in,
+                                    const unsigned* maxbits, uint16_t* out, float* scale,
+                                    void* stream)
+{
+    // enough blocks to fill the GPU, each streaming a large contiguous share
+    int64_t bx = (npix + kQThreads * 32 - 1) / (kQThreads * 32);
+    if (bx > 1024) bx = 1024;
+    if (bx < 1) bx = 1;
+    hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)bx, (unsigned)np), dim3(kQThreads), 0,
+                       (hipStream_t)stream, in, npix, maxbits, out, scale);
+    return check_launch("quantize kernel");
+}
+
 fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16_t* out,
                                float* scale, void* stream)
 {
@@ -118,25 +138,16 @@ fdk_status launch_quantize_f16(int32_t np, int64_t npix, const float* in, uint16
     fdk_status s = device_alloc_async((size_t)np * sizeof(unsigned), stream, &d_max);
     if (s != FDK_OK) return s;
     unsigned* mx = (unsigned*)d_max;
-    hipLaunchKernelGGL(clear_u32, dim3((np + 255) / 256), dim3(256), 0, st, mx, np);
-    s = check_launch("clear kernel");
-    // enough blocks to fill the GPU, each streaming a large contiguous share
+    s = launch_clear_u32(mx, np, stream);
     int64_t bmax = (npix + kQThreads * 16 - 1) / (kQThreads * 16);
     if (bmax < 1) bmax = 1;
     const int64_t bm = bmax < 16 ? bmax : 16;
-    int64_t bx = (npix + kQThreads * 32 - 1) / (kQThreads * 32);
-    if (bx > 1024) bx = 1024;
-    if (bx < 1) bx = 1;
     if (s == FDK_OK) {
         hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)bm, (unsigned)np), dim3(kQThreads), 0, st,
                            in, npix, mx);
         s = check_launch("absmax kernel");
     }
-    if (s == FDK_OK) {
-        hipLaunchKernelGGL(quantize_kernel, dim3((unsigned)bx, (unsigned)np), dim3(kQThreads), 0,
-                           st, in, npix, (const unsigned*)mx, out, scale);
-        s = check_launch("quantize kernel");
-    }
+    if (s == FDK_OK) s = launch_quantize_with_max(np, npix, in, mx, out, scale, stream);
     fdk_status s2 = device_free_async(d_max, stream);
     return s != FDK_OK ? s : s2;
 }

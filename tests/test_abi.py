@@ -145,14 +145,23 @@ def test_slab_range_rejected():
 def test_filter_quantize_phantom_validation():
     sg = _lib.stack_struct(4, 8, 16)
     L = _lib.lib
-    assert L.fdk_filter(ctypes.byref(sg), None, FAKE, 1.0, 1.0, 500.0, 1000.0, 0, 0, 6.28, 4,
-                        None) == E_INVALID
-    assert L.fdk_filter(ctypes.byref(sg), FAKE, FAKE, 1.0, 1.0, 500.0, 1000.0, 0, 0, 6.28, 4,
-                        None) == E_INVALID                      # raw == out
-    assert L.fdk_filter(ctypes.byref(sg), FAKE, ctypes.c_void_p(0x20000), -1.0, 1.0, 500.0,
+    OUT = ctypes.c_void_p(0x20000)
+    SC = ctypes.c_void_p(0x30000)
+    assert L.fdk_filter(ctypes.byref(sg), None, 0, FAKE, None, 1.0, 1.0, 500.0, 1000.0, 0, 0,
+                        6.28, 4, None) == E_INVALID
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 0, FAKE, None, 1.0, 1.0, 500.0, 1000.0, 0, 0,
+                        6.28, 4, None) == E_INVALID                 # raw == out
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 0, OUT, None, -1.0, 1.0, 500.0,
                         1000.0, 0, 0, 6.28, 4, None) == E_INVALID
-    assert L.fdk_filter(ctypes.byref(sg), FAKE, ctypes.c_void_p(0x20000), 1.0, 1.0, 500.0,
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 0, OUT, None, 1.0, 1.0, 500.0,
                         1000.0, 0, 0, 6.28, 0, None) == E_INVALID
+    # output dtype and scale array must agree
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 1, OUT, None, 1.0, 1.0, 500.0,
+                        1000.0, 0, 0, 6.28, 4, None) == E_INVALID     # f16 without scale
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 0, OUT, SC, 1.0, 1.0, 500.0,
+                        1000.0, 0, 0, 6.28, 4, None) == E_INVALID     # f32 with scale
+    assert L.fdk_filter(ctypes.byref(sg), FAKE, 2, OUT, SC, 1.0, 1.0, 500.0,
+                        1000.0, 0, 0, 6.28, 4, None) == E_INVALID     # unknown dtype
     assert L.fdk_quantize_f16(0, 8, 16, FAKE, FAKE, FAKE, None) == E_INVALID
     assert L.fdk_quantize_f16(4, 8, 16, FAKE, FAKE, None, None) == E_INVALID
     ell = np.zeros((2, 16))
@@ -166,6 +175,20 @@ def test_filter_quantize_phantom_validation():
     bad[1, 4] = 0.0
     assert L.fdk_phantom_project(_lib.ptr(bad), 2, ctypes.byref(sg), FAKE, *args, 0, 4,
                                  None) == E_INVALID             # zero semi-axis
+
+
+def test_peak_microbenchmarks_validate():
+    L = _lib.lib
+    n = ctypes.c_int64(0)
+    assert L.fdk_peak_hbm_read(None, 1024, 8, FAKE, None) == E_INVALID
+    assert L.fdk_peak_hbm_read(FAKE, 1000, 8, FAKE, None) == E_INVALID          # not 16 * k
+    assert L.fdk_peak_hbm_read(ctypes.c_void_p(0x10004), 1024, 8, FAKE, None) == E_INVALID
+    assert L.fdk_peak_hbm_read(FAKE, 1024, 0, FAKE, None) == E_INVALID
+    assert L.fdk_peak_lds_read(6, 8, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_lds_read(0, 0, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_lds_read(0, 8, 1, None, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_valu_fma(8, 0, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_valu_fma(8, 1, FAKE, None, None) == E_INVALID
 
 
 def test_status_strings():
@@ -195,15 +218,16 @@ def test_circular_matrices_match_ray_plane_geometry():
         fdk.circular_matrices(4, scan["arc"], 0.0, -1.0, 990.0, nh, nw, 1.0, 1.0)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c4", "c5"])
-def test_plan_covers_every_footprint(name):
+@pytest.mark.parametrize("name,f16", [("c1", False), ("c2", False), ("c2", True), ("c3", False),
+                                      ("c3", True), ("c4", False), ("c5", False)])
+def test_plan_covers_every_footprint(name, f16):
     """The launch plan bounds the footprint of every block and view (checked
     here by brute force over tiles, chunks and views, in FP64, with the
     kernel's own rule): every half-chunk fits the LDS rows, every whole chunk
     fits rows_full, every width fits the pitch."""
     cfg = wl.CONFIGS[name]
     m = og.scan_matrices(cfg["scan"], cfg["np"], cfg["nh"], cfg["nw"])
-    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], cfg["np"], cfg["nh"], cfg["nw"], m)
+    plan = fdk.bp_plan(cfg["shape"], cfg["voxel"], cfg["np"], cfg["nh"], cfg["nw"], m, f16=f16)
     M = og.index_matrices(m, cfg["shape"], cfg["voxel"])
     nz, ny, nx = cfg["shape"]
     kz = plan["kz"]

@@ -13,7 +13,8 @@ import pytest
 import oracle
 from oracle import geometry as og
 import workloads as wl
-from helpers import c1_filtered, log, rel
+from helpers import (c1_filtered, gpu_phantom_stacks, log, rel, subblock_errors,
+                     whole_rel)
 
 pytestmark = pytest.mark.gpu
 
@@ -237,6 +238,53 @@ def test_c3_full_size_sampled_f16():
     e = rel(got, ref)
     log("c3 sampled rel-L2", e)
     assert e <= TOL32
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_benchmark_stack_subblocks(name):
+    """The benchmark's own input and launches: GPU phantom line integrals
+    filtered into float32 and (same filter call, binary16 output) into
+    binary16 + per-view scale, both back-projected at full size.  The binary16
+    stack is bit-equal to the stand-alone pre-pass applied to the float32
+    one; over eight 64^3 sub-blocks (centre, corners, edges) against the FP64
+    oracle on each view's window: float32 storage <= 1e-5, binary16 storage
+    <= 1e-3 against the oracle on the float32 stack and <= 1e-5 against the
+    oracle on the dequantised stack; binary16 against float32 storage over
+    the whole volume <= 1e-3."""
+    cfg = wl.CONFIGS[name]
+    log(name, "benchmark stacks", cfg["shape"], (cfg["np"], cfg["nh"], cfg["nw"]))
+    filt, h, sc, mats = gpu_phantom_stacks(cfg)
+    hq, sq = fdk.quantize_f16(filt)
+    torch.cuda.synchronize()
+    assert torch.equal(hq.view(torch.int16), h.view(torch.int16))
+    assert torch.equal(sq.view(torch.int32), sc.view(torch.int32))
+    del hq, sq
+    vol32 = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    vol16 = torch.zeros(cfg["shape"], dtype=torch.float32, device="cuda")
+    fdk.backproject(vol32, filt, mats, cfg["voxel"])
+    fdk.backproject(vol16, h, mats, cfg["voxel"], scale=sc)
+    torch.cuda.synchronize()
+    whole = whole_rel(vol16, vol32)
+    log(name, "binary16 vs float32 storage, whole volume", whole)
+    errs = subblock_errors(cfg, mats, filt, h, sc, vol32, vol16)
+    log(name, "sub-blocks", errs)
+    del filt, h, sc, vol32, vol16
+    torch.cuda.empty_cache()
+    assert errs["f32"] <= TOL32
+    assert errs["f16"] <= TOL16
+    assert errs["f16_dequantised"] <= TOL32
+    assert whole <= TOL16
+
+
+def test_binding_rejects_scale_of_wrong_length():
+    """A per-view scale array shorter than the stack would be read past its
+    end on the device: the binding refuses it."""
+    vol = torch.zeros((4, 8, 8), dtype=torch.float32, device="cuda")
+    h = torch.zeros((3, 16, 16), dtype=torch.float16, device="cuda")
+    mats = og.scan_matrices(wl.CONFIGS["c1"]["scan"], 3, 16, 16)
+    for bad in (torch.ones(2, device="cuda"), torch.ones((3, 1), device="cuda")):
+        with pytest.raises(ValueError):
+            fdk.backproject(vol, h, mats, (1.0, 1.0, 1.0), scale=bad)
 
 
 def test_p10_1300cube_sampled():

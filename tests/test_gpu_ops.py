@@ -212,6 +212,52 @@ def test_filter_ragged_rows(nw):
     assert rel(out.cpu().numpy(), ref) <= TOL32
 
 
+F16_FILTER_CASES = [
+    # (np, nh, nw), raw: "phantom" (C1 phantom views) or "gaussian"
+    ((64, 128, 128), "phantom"),
+    ((5, 3, 7), "gaussian"),          # odd rows: a row pair spans two views
+    ((6, 9, 2049), "gaussian"),       # direct-convolution rows, odd nh
+    ((10, 2048, 2048), "gaussian"),   # three chunks of the 64 MiB workspace (4 + 4 + 2 views)
+]
+
+
+@pytest.mark.parametrize("case", range(len(F16_FILTER_CASES)))
+def test_filter_f16_output(case):
+    """fdk_filter with binary16 output = the FP16 storage rule applied to its
+    own float32 output (bit for bit, both against the library's stand-alone
+    pre-pass and against the oracle's rule), and within the binary16 rounding
+    of the FP64 filter."""
+    (npv, nh, nw), kind = F16_FILTER_CASES[case]
+    scan = dict(sod=600.0, sdd=1100.0, du=0.8, dv=1.2, arc=2 * math.pi, theta0=0.0,
+                u_off=1.5, v_off=-0.5)
+    if kind == "phantom":
+        cfg = wl.CONFIGS["c1"]
+        scan = cfg["scan"]
+        raw = oph.line_integrals(wl.config_ellipsoids(cfg, 0), scan, npv, nh, nw).astype(np.float32)
+        raw[3] = 0.0                                 # an all-zero view: scale 1
+        raw[5] *= np.float32(1e-20)                  # tiny values: binary16 subnormals
+    else:
+        raw = wl.gaussian(700 + case, (npv, nh, nw))
+    raw_d = torch.from_numpy(raw).cuda()
+    out32 = fdk.fdk_filter(raw_d, scan, np_total=360)
+    h, s = fdk.fdk_filter(raw_d, scan, np_total=360, dtype=torch.float16)
+    hq, sq = fdk.quantize_f16(out32)
+    torch.cuda.synchronize()
+    assert torch.equal(h.view(torch.int16), hq.view(torch.int16))
+    assert torch.equal(s.view(torch.int32), sq.view(torch.int32))
+    h_ref, s_ref = oracle.quantize_f16(out32.cpu().numpy())
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), s_ref.view(np.uint32))
+    assert np.array_equal(h.cpu().numpy().view(np.uint16), h_ref.view(np.uint16))
+    nv = min(npv, 2)                                 # FP64 filter on the first views
+    ref = oracle.fdk_filter(raw[:nv].astype(np.float64), scan, np_total=360)
+    deq = (h[:nv].float() * s[:nv, None, None]).cpu().numpy()
+    e = rel(deq, ref)
+    log("filter f16 case", case, "rel-L2 of the dequantised output vs FP64 filter", e)
+    assert e <= 1e-3
+    del raw_d, out32, h, s, hq, sq
+    torch.cuda.empty_cache()
+
+
 def test_phantom_projector_parity():
     cfg = wl.CONFIGS["c1"]
     scan = dict(cfg["scan"], theta0=0.25, u_off=0.5, v_off=-1.5)
@@ -244,6 +290,24 @@ def test_fdk_pipeline_on_gpu():
     e = rel(vol.cpu().numpy(), ref)
     log("pipeline rel-L2", e)
     assert e <= 1e-5
+
+
+def test_forward_projection_c4_full_size_views():
+    """The C4 launch itself (256^3 at 0.25 mm, 360 views, 384^2 detector):
+    element-wise against the oracle on eight of the 360 views (all quadrants,
+    both lane axes of the voxel-driven kernel)."""
+    cfg = wl.CONFIGS["c4"]
+    npv, nh, nw = cfg["np"], cfg["nh"], cfg["nw"]
+    mats = og.scan_matrices(cfg["scan"], npv, nh, nw)
+    x = wl.gaussian(4101, cfg["shape"])
+    log("c4 fp: gpu")
+    got = gpu_fp(x, mats, nh, nw, cfg["voxel"])
+    sel = np.array([0, 45, 89, 90, 137, 180, 271, 359])
+    log("c4 fp: oracle on views", sel)
+    ref = oracle.forwardproject(x.astype(np.float64), mats[sel], nh, nw, cfg["voxel"])
+    e = rel(got[sel], ref)
+    log("c4 fp: rel-L2 on 8 views", e)
+    assert e <= TOL32
 
 
 @pytest.fixture

@@ -42,9 +42,11 @@ sys.path.insert(0, ROOT)
 # math: v = v0 + k dv (1), fraction and row of v (2), two horizontal lerps
 # (2 + 2), one vertical lerp (2), weighted accumulation (1).
 OPS_PER_UPDATE = 10
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = issue rate of non-packed
-# FP32 VALU lane-operations.
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X vector FP32 peak: 157.3 TFLOP/s counting an FMA as two flops, i.e.
+# 256 CUs x 128 FP32 lane-operations per clock x 2.4 GHz = 78.6 T lane-ops/s.
+# (Non-packed FMAs reach it: the fdk_peak_valu_fma microbenchmark issues
+# v_fma_f32 at 68 T lane-ops/s, well above a 64-lane-per-clock reading.)
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # Nominal LDS bandwidth: 128 bytes per clock per CU.
 LDS_NOMINAL_GBS = 256 * 128 * 2.4e9 / 1e9

@@ -220,8 +220,9 @@ fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, const double* 
 /* Message of the last error on the calling thread ("" if none). */
 const char* fdk_last_error(void);
 
-/* Static description of a status code. */
-const char* fdk_status_string(fdk_status s);
+/* Static description of a status code; any value is accepted ("unknown
+ * status" for values that are not an fdk_status). */
+const char* fdk_status_string(int32_t s);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,16 @@
  *                            detector's centre row on the orbit plane and the
  *                            volume centred on it), else FDK_E_GEOMETRY; whole
  *                            volume only; nb is ignored.
+ *   FDK_VARIANT_SUBLINE      production structure with the sub-line
+ *                            interpolation of Section 3.1.5 (Algorithm 1's
+ *                            sub-line step): per (column, view) the detector
+ *                            columns floor(u) and floor(u) + 1 are blended
+ *                            once, along every row the column's slices reach,
+ *                            into a line in LDS; each update is one 1-D
+ *                            interpolation along that line.  The window holds
+ *                            the whole chunk's footprint; whole volume only;
+ *                            FDK_E_UNSUPPORTED if window and lines do not fit
+ *                            in LDS; nb is ignored.
  *
  * nb: views per batch, 1 <= nb (values above np mean np).  proj: device
  * float32 [np][nh][nw] (sg->dtype must be FDK_F32, else FDK_E_UNSUPPORTED);
@@ -49,7 +59,8 @@ typedef enum {
     FDK_VARIANT_PRODUCTION = 0,
     FDK_VARIANT_GLOBAL_TAPS = 1,
     FDK_VARIANT_LISTING1 = 2,
-    FDK_VARIANT_SYMMETRY = 3
+    FDK_VARIANT_SYMMETRY = 3,
+    FDK_VARIANT_SUBLINE = 4
 } fdk_bp_variant;
 
 fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const fdk_volume* vg, float* vol,

@@ -67,6 +67,33 @@ fdk_status fdk_peak_lds_read(int32_t pattern, int32_t blocks, int32_t iters, uin
 fdk_status fdk_peak_valu_fma(int32_t blocks, int32_t iters, float* sink, int64_t* ops_out,
                              void* stream);
 
+/* Instructions of fdk_peak_valu_op: the VALU instructions of the
+ * back-projector's hot loop. */
+typedef enum {
+    FDK_OP_FMA_F32 = 0,      /* v_fma_f32 (VOP3), float32 */
+    FDK_OP_FMAC_F32 = 1,     /* v_fmac_f32 (VOP2), float32, accumulator in place */
+    FDK_OP_SUB_F32 = 2,      /* v_sub_f32 */
+    FDK_OP_FRACT_F32 = 3,    /* v_fract_f32 */
+    FDK_OP_CVT_I32_F32 = 4,  /* v_cvt_i32_f32 */
+    FDK_OP_MAD_U32_U24 = 5,  /* v_mad_u32_u24 (24-bit integer multiply-add) */
+    FDK_OP_FMA_MIX_F32 = 6,  /* v_fma_mix_f32 with one binary16 operand (FP32 arithmetic) */
+    FDK_OP_CVT_F32_F16 = 7,  /* v_cvt_f32_f16 */
+    FDK_OP_DOT2_F32_F16 = 8, /* v_dot2_f32_f16 */
+    FDK_OP_PK_FMA_F16 = 9,   /* v_pk_fma_f16 (two binary16 lanes) */
+    FDK_OP_ADD_U32 = 10,     /* v_add_u32 */
+    FDK_OP_FLOOR_F32 = 11    /* v_floor_f32 */
+} fdk_valu_op;
+
+/*
+ * fdk_peak_valu_op -- the issue rate of one VALU instruction: `blocks` blocks
+ * of 256 threads, each thread running 8 independent chains of iters x 16
+ * instructions `op` (fdk_valu_op), written as inline assembly so that exactly
+ * that instruction is issued.  *ops_out (host) receives the lane-operations
+ * (threads x 8 x 16 x iters).  iters >= 1, blocks >= 1, else FDK_E_INVALID.
+ */
+fdk_status fdk_peak_valu_op(int32_t op, int32_t blocks, int32_t iters, float* sink,
+                            int64_t* ops_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,8 +49,12 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_SO)
+            # ORACLE_LIBRARY: another build of oracle.c (e.g. with sanitizers)
+            path = os.environ.get("ORACLE_LIBRARY")
+            if not path:
+                build()
+                path = _SO
+            lib = ctypes.CDLL(path)
             vol = [_I64] * 3 + [_D] * 6
             stk = [_I64] * 3 + [_P] * 3
             lib.oracle_bp.argtypes = vol + stk + [_P, _P, ctypes.c_int]

@@ -73,6 +73,7 @@ def _load():
         "fdk_peak_hbm_read": [P, ctypes.c_int64, I, P, P],
         "fdk_peak_lds_read": [I, I, I, P, P, P],
         "fdk_peak_valu_fma": [I, I, P, P, P],
+        "fdk_peak_valu_op": [I, I, I, P, P, P],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -88,13 +89,15 @@ def _load():
 lib = _load()
 
 #: names declared in include/fdk.h, include/fdk_learn.h and include/fdk_ablation.h
-EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_forwardproject", "fdk_filter",
+EXPORTS = ("fdk_backproject", "fdk_backproject_slab",
+           "fdk_forwardproject", "fdk_filter",
            "fdk_quantize_f16", "fdk_circular_matrices", "fdk_phantom_project", "fdk_bp_plan",
            "fdk_last_error", "fdk_status_string",
            "fdk_cosine_weight", "fdk_conv1d_forward", "fdk_conv1d_backward_data",
            "fdk_conv1d_backward_weight", "fdk_sqerr", "fdk_adam",
            "fdk_backproject_variant",
-           "fdk_peak_hbm_read", "fdk_peak_lds_read", "fdk_peak_valu_fma")
+           "fdk_peak_hbm_read", "fdk_peak_lds_read", "fdk_peak_valu_fma",
+           "fdk_peak_valu_op")
 
 
 def check(code: int) -> None:

@@ -9,7 +9,12 @@ Variants of the same back-projection (float32 projections):
   of Section 3.2 removed (taps read from global memory);
 * ``listing1``: Listing 1 as a GPU kernel (thread per voxel, full
   projection per (voxel, view), taps from global memory), with the volume
-  updated once per batch of nb views.
+  updated once per batch of nb views;
+* ``symmetry``: the geometric symmetry of Section 3.1.2 (slices k and
+  nz-1-k share v's row, fraction and LDS address);
+* ``subline``: the sub-line interpolation of Section 3.1.5 (two detector
+  columns blended once per (column, view) into an LDS line, one 1-D
+  interpolation per update).
 
     python -m paper_2104_13248_amd.ablations [--config c2] [--views N]
 
@@ -26,9 +31,9 @@ import sys
 import torch
 
 from . import backproject, scan_matrices
-from ._lib import FDK_F32, check, host_f64, lib, ptr, stack_struct, volume_struct
+from ._lib import FDK_F32, FdkError, check, host_f64, lib, ptr, stack_struct, volume_struct
 
-VARIANTS = {"production": 0, "global_taps": 1, "listing1": 2, "symmetry": 3}
+VARIANTS = {"production": 0, "global_taps": 1, "listing1": 2, "symmetry": 3, "subline": 4}
 
 
 def backproject_variant(vol: torch.Tensor, proj: torch.Tensor, mats, voxel, variant: str,
@@ -91,6 +96,8 @@ def sweep(config: str = "c2", views: int | None = None, nbs=(1, 2, 4, 8, 16, 32,
     emit("production", npv, _time(lambda: backproject(vol, proj, mats, cfg["voxel"]), reps))
     emit("symmetry", npv, _time(lambda: backproject_variant(vol, proj, mats, cfg["voxel"],
                                                             "symmetry"), reps))
+    emit("subline", npv, _time(lambda: backproject_variant(vol, proj, mats, cfg["voxel"],
+                                                           "subline"), reps))
     emit("global_taps", npv, _time(lambda: backproject_variant(vol, proj, mats, cfg["voxel"],
                                                                "global_taps"), reps))
     for nb in nbs:
@@ -106,13 +113,47 @@ def sweep(config: str = "c2", views: int | None = None, nbs=(1, 2, 4, 8, 16, 32,
     return rows
 
 
+def compare_problem(name: str, reps: int = 2, out=sys.stdout):
+    """Production against the sub-line and symmetric organisations on one of
+    the paper's problem sizes (Table 3; geometry reading of problems.py)."""
+    from . import problems
+    shape, voxel, mats, nh, nw = problems.geometry(name)
+    npv = problems.VIEWS
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9100 + int(name[1:]))
+    proj = torch.randn((npv, nh, nw), generator=g, device="cuda")
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    n_upd = vol.numel() * npv
+    rows = []
+    for variant in ("production", "subline", "symmetry"):
+        fn = (lambda: backproject(vol, proj, mats, voxel)) if variant == "production" else \
+            (lambda: backproject_variant(vol, proj, mats, voxel, variant))
+        r = {"problem": name, "detector": nh, "volume": shape[0], "views": npv,
+             "variant": variant}
+        try:
+            ms = _time(fn, reps)
+            r.update(ms=ms, gups=n_upd / (ms * 1e-3) / 1e9)
+        except FdkError as e:           # e.g. window and lines beyond the LDS
+            r.update(unsupported=str(e))
+        rows.append(r)
+        print(json.dumps(r), file=out, flush=True)
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="back-projection ablations on one GPU")
     ap.add_argument("--config", default="c2")
     ap.add_argument("--views", type=int, default=None, help="views (default: the workload's)")
+    ap.add_argument("--problem", default=None,
+                    help="comma-separated problems of Table 3 (P1..P10): production, sub-line "
+                         "and symmetric organisations only")
     ap.add_argument("--reps", type=int, default=2)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
+    if a.problem:
+        for name in a.problem.split(","):
+            compare_problem(name, a.reps)
+        return
     sweep(a.config, a.views, reps=a.reps)
 
 

@@ -45,12 +45,13 @@ def _newer(src_paths, dst):
     return any(os.path.getmtime(p) > t for p in src_paths)
 
 
-def _compile(src: str, force: bool) -> str:
+def _compile(src: str, force: bool, build_dir: str = BUILD, extra=()) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(BUILD, src + ".o")
-    deps = [path, os.path.join(INCLUDE, "fdk.h")] + [os.path.join(CSRC, h) for h in HEADERS]
+    obj = os.path.join(build_dir, src + ".o")
+    deps = [path] + [os.path.join(INCLUDE, h) for h in os.listdir(INCLUDE) if h.endswith(".h")] + \
+        [os.path.join(CSRC, h) for h in HEADERS]
     if force or _newer(deps, obj):
-        cmd = [HIPCC, "-c"] + COMMON + DEVICE + [path, "-o", obj]
+        cmd = [HIPCC, "-c"] + COMMON + DEVICE + list(extra) + [path, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(map(shlex.quote, cmd)),
@@ -58,19 +59,23 @@ def _compile(src: str, force: bool) -> str:
     return obj
 
 
-def build(force: bool = False, jobs: int = 0) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(force: bool = False, jobs: int = 0, lib_path: str = LIB, build_dir: str = BUILD,
+          extra=()) -> str:
+    """Compile every source into ``build_dir`` and link ``lib_path``.  ``extra``
+    are additional hipcc flags for every compile and the link (e.g. host-only
+    sanitizers, each ``-fsanitize=`` after ``-Xarch_host``)."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 16)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, force), SOURCES))
-    if force or _newer(objs, LIB):
-        tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+        objs = list(ex.map(lambda s: _compile(s, force, build_dir, extra), SOURCES))
+    if force or _newer(objs, lib_path):
+        tmp = lib_path + ".tmp%d" % os.getpid()
+        cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + list(extra) + ["-o", tmp] + objs
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

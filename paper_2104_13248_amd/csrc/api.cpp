@@ -370,18 +370,20 @@ extern "C" fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const
     if (!vol || !proj) return fail(FDK_E_INVALID, "volume/projection pointer is NULL");
     if (nb < 1) return fail(FDK_E_INVALID, "nb must be at least 1");
     if (variant != FDK_VARIANT_PRODUCTION && variant != FDK_VARIANT_GLOBAL_TAPS &&
-        variant != FDK_VARIANT_LISTING1 && variant != FDK_VARIANT_SYMMETRY)
+        variant != FDK_VARIANT_LISTING1 && variant != FDK_VARIANT_SYMMETRY &&
+        variant != FDK_VARIANT_SUBLINE)
         return fail(FDK_E_INVALID, "unknown back-projection variant");
     const int32_t batch = nb < sg->np ? nb : sg->np;
-    if (variant == FDK_VARIANT_SYMMETRY) {
-        if (!bp_geometry_symmetric(*vg, *sg, M))
+    if (variant == FDK_VARIANT_SYMMETRY || variant == FDK_VARIANT_SUBLINE) {
+        const bool sym = variant == FDK_VARIANT_SYMMETRY;
+        if (sym && !bp_geometry_symmetric(*vg, *sg, M))
             return fail(FDK_E_GEOMETRY,
                         "the symmetric variant needs v(nz-1-k) = nh-1-v(k) in every view (detector "
                         "centre row on the orbit plane, volume centred on it)");
         if ((int64_t)sg->nh * sg->nw * 4 >= (1ll << 31))
             return fail(FDK_E_UNSUPPORTED, "one view larger than 2 GiB");
         BpPlan plan;
-        s = make_bp_plan_sym(*vg, *sg, M, plan);
+        s = sym ? make_bp_plan_sym(*vg, *sg, M, plan) : make_bp_plan_subline(*vg, *sg, M, plan);
         if (s != FDK_OK) return s;
         const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
         void* d_world = nullptr;
@@ -402,7 +404,8 @@ extern "C" fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const
             a.dx = vg->dx; a.dy = vg->dy; a.dz = vg->dz;
             fill_grid(*vg, a.ox, a.oy, a.oz);
             a.f16 = 0;
-            s = launch_backproject_sym(a, plan, stream);
+            s = sym ? launch_backproject_sym(a, plan, stream)
+                    : launch_backproject_subline(a, plan, stream);
         }
         fdk_status s2 = FDK_OK;
         for (void* d : {d_index, d_world})

@@ -486,6 +486,113 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     }
 }
 
+// Sub-line variant (Section 3.1.5 and Algorithm 1's sub-line step): per
+// (column, view) the detector columns floor(u) and floor(u) + 1 are blended
+// once, with the column's weight fu, along every row its KZ slices reach,
+// into a line in LDS; each update is then one 1-D interpolation along that
+// line.  Lines are stored row-major with the thread index fastest
+// ([line_rows][256] words): a lane reads and writes only its own column of
+// them, so the lanes of a wave meet in distinct banks whatever their rows and
+// no barrier is needed between blending and use.  The window holds every
+// whole-chunk footprint (the plan sizes it so); float32 stacks only.
+template <int KZ, int PITCH>
+__global__ __launch_bounds__(kThreads) void bp_subline_kernel(const BpArgs A, int line_rows)
+{
+    extern __shared__ float smem[];
+    float* tile = smem;                                       // [rows][PITCH] words
+    float* lines = smem + A.rows * PITCH;                     // [line_rows][kThreads]
+    ViewRec* vtab = reinterpret_cast<ViewRec*>(lines + line_rows * kThreads);
+
+    const BlockPos bp = block_position(blockIdx.x, A.ntiles_pad);
+    const int t_id = bp.tile, chunk_local = bp.chunk_local;
+    if (t_id >= A.ntiles) return;                             // padding block
+    const int tx = t_id % A.ntx, ty = t_id / A.ntx;
+    const int kc = (A.chunk_first + chunk_local) * KZ;
+    const int i0 = tx * kTile, j0 = ty * kTile;
+    const int ni = min(kTile, A.nx - i0), nj = min(kTile, A.ny - j0);
+
+    const int tid = threadIdx.x;
+    const int wave = uniform(tid >> 6), lane = tid & 63;
+    const int lx = tid & (kTile - 1), ly = tid >> 4;
+    const bool active = lx < ni && ly < nj;
+    const float di = (float)min(lx, ni - 1), dj = (float)min(ly, nj - 1);
+
+    const char* proj = reinterpret_cast<const char*>(A.proj);
+    const unsigned row_bytes = (unsigned)A.nw * 4u;
+    const unsigned view_bytes = row_bytes * (unsigned)A.nh;
+    float* myline = lines + tid;
+
+    float acc[KZ];
+#pragma unroll
+    for (int kk = 0; kk < KZ; ++kk) acc[kk] = 0.f;
+
+    for (int sb = 0; sb < A.np; sb += kViewBatch) {
+        const int nb = min(kViewBatch, A.np - sb);
+        __syncthreads();
+        if (tid < nb) {
+            const int s = sb + tid;
+            view_record(A.M + 12 * (size_t)s, i0, j0, ni, nj, kc, KZ, 1.0f, PITCH, A.rows, false,
+                        &vtab[tid]);
+        }
+        __syncthreads();
+        for (int qv = 0; qv < nb; ++qv) {
+            const ViewRec& rv = vtab[qv];
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)(proj + (size_t)(sb + qv) * view_bytes), 0, (int)view_bytes, kBufferFlags);
+            stage_rows<PITCH, false>(tile, A.rows, rs, A.nh, row_bytes, A.nw, uniform(rv.r0),
+                                     uniform(rv.c0), uniform(rv.R), uniform(rv.C), wave, lane);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            const float w = fmaf(uniform(rv.d), di, fmaf(uniform(rv.e), dj, uniform(rv.w0)));
+            float F = __builtin_amdgcn_rcpf(w);
+            F = F * fmaf(-w, F, 2.0f);                        // one Newton step
+            const float u = fmaf(uniform(rv.a), di, fmaf(uniform(rv.b), dj, uniform(rv.N0))) * F;
+            const float dv = uniform(rv.m12) * F;
+            const float W = F * F;
+            const float fu = __builtin_amdgcn_fractf(u);
+            const HalfBase& hb = rv.half[0];
+            // v of slice kc relative to window row 0
+            const float v0 = fmaf(fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))), F,
+                                  (float)uniform(hb.row));
+            // first line row one below the lowest row reached (>= 0: the window
+            // starts a row below every footprint), so that v - m0 >= 1 - rounding
+            // and (int) is the floor for every slice
+            const float vlo = fminf(v0, fmaf((float)(KZ - 1), dv, v0));
+            const int m0 = (int)vlo - 1;
+            // ---- the column's line: columns floor(u), floor(u) + 1 blended with fu
+            const float* col = tile + (int)u;
+            for (int m = 0; m < line_rows; ++m) {
+                const int r = min(m0 + m, A.rows - 1);
+                const float p0 = col[r * PITCH], p1 = col[r * PITCH + 1];
+                myline[m * kThreads] = fmaf(fu, p1 - p0, p0);
+            }
+            // ---- updates: one 1-D interpolation along the line each
+            const float vb = v0 - (float)m0;
+#pragma unroll
+            for (int t = 0; t < KZ; ++t) {
+                const float v = fmaf((float)t, dv, vb);
+                const int r = (int)v;
+                const float fv = __builtin_amdgcn_fractf(v);
+                const float l0 = myline[r * kThreads], l1 = myline[(r + 1) * kThreads];
+                acc[t] = fmaf(W, fmaf(fv, l1 - l0, l0), acc[t]);
+            }
+            __syncthreads();                                  // tile is overwritten next
+        }
+    }
+
+    if (active) {
+        const int i = i0 + lx, j = j0 + ly;
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) {
+            const int k = kc + kk;
+            if (k < A.nz) {
+                float* dst = A.vol + ((size_t)k * A.ny + j) * A.nx + i;
+                *dst += acc[kk];
+            }
+        }
+    }
+}
+
 // Four waves per SIMD: the register budget that, with the LDS tile of the
 // launch plan, keeps four or more blocks resident per CU.
 template <int KZ, int PITCH, bool F16>
@@ -636,6 +743,36 @@ fdk_status launch_sym_kz(const BpArgs& a, int pitch, bool f16, size_t lds, unsig
 }
 
 template <int KZ, int PITCH>
+fdk_status launch_subline_pitch(const BpArgs& a, int line_rows, size_t lds, unsigned blocks,
+                                hipStream_t st)
+{
+    if (lds > 64 * 1024) {
+        if (hipFuncSetAttribute((const void*)bp_subline_kernel<KZ, PITCH>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return fail(FDK_E_DEVICE, "cannot raise the LDS limit of the sub-line kernel");
+    }
+    hipLaunchKernelGGL((bp_subline_kernel<KZ, PITCH>), dim3(blocks), dim3(kThreads), lds, st, a,
+                       line_rows);
+    return check_launch("sub-line back-projection kernel");
+}
+
+template <int KZ>
+fdk_status launch_subline_kz(const BpArgs& a, int pitch, int line_rows, size_t lds,
+                             unsigned blocks, hipStream_t st)
+{
+    switch (pitch) {
+        case 40: return launch_subline_pitch<KZ, 40>(a, line_rows, lds, blocks, st);
+        case 56: return launch_subline_pitch<KZ, 56>(a, line_rows, lds, blocks, st);
+        case 72: return launch_subline_pitch<KZ, 72>(a, line_rows, lds, blocks, st);
+        case 88: return launch_subline_pitch<KZ, 88>(a, line_rows, lds, blocks, st);
+        case 120: return launch_subline_pitch<KZ, 120>(a, line_rows, lds, blocks, st);
+        case 184: return launch_subline_pitch<KZ, 184>(a, line_rows, lds, blocks, st);
+        case 248: return launch_subline_pitch<KZ, 248>(a, line_rows, lds, blocks, st);
+    }
+    return fail(FDK_E_UNSUPPORTED, "no kernel for this LDS pitch");
+}
+
+template <int KZ, int PITCH>
 fdk_status launch_kz_pitch(const BpArgs& a, bool f16, size_t lds, unsigned blocks, hipStream_t st)
 {
     const void* fn = f16 ? (const void*)bp_kernel<KZ, PITCH, true>
@@ -730,6 +867,36 @@ fdk_status launch_backproject_sym(const BpLaunch& a, const BpPlan& plan, void* s
         case 8: return launch_sym_kz<8>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
         case 16: return launch_sym_kz<16>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
         case 32: return launch_sym_kz<32>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
+    }
+    return fail(FDK_E_UNSUPPORTED, "no kernel for this slice count");
+}
+
+fdk_status launch_backproject_subline(const BpLaunch& a, const BpPlan& plan, void* stream)
+{
+    hipStream_t st = (hipStream_t)stream;
+    fdk_status s = launch_compose(a.mats_world, a.mats_index, a.np, a.dx, a.dy, a.dz, a.ox, a.oy,
+                                  a.oz, stream);
+    if (s != FDK_OK) return s;
+    BpArgs A;
+    A.proj = a.proj;
+    A.scale = nullptr;
+    A.M = a.mats_index;
+    A.vol = a.vol;
+    A.nx = a.nx; A.ny = a.ny; A.nz = a.nz; A.np = a.np; A.nh = a.nh; A.nw = a.nw;
+    A.k_begin = 0;
+    A.k_end = a.nz;
+    A.ntx = plan.ntx;
+    A.ntiles = plan.ntx * plan.nty;
+    A.ntiles_pad = plan.ntiles_pad;
+    A.chunk_first = 0;
+    A.rows = plan.rows;
+    const int64_t blocks = (int64_t)plan.ntiles_pad * plan.nchunks;
+    if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "grid too large");
+    const size_t lds = (size_t)plan.lds_bytes;
+    switch (plan.kz) {
+        case 8: return launch_subline_kz<8>(A, plan.pitch, plan.line_rows, lds, (unsigned)blocks, st);
+        case 16: return launch_subline_kz<16>(A, plan.pitch, plan.line_rows, lds, (unsigned)blocks, st);
+        case 32: return launch_subline_kz<32>(A, plan.pitch, plan.line_rows, lds, (unsigned)blocks, st);
     }
     return fail(FDK_E_UNSUPPORTED, "no kernel for this slice count");
 }

@@ -366,6 +366,60 @@ fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
     return FDK_OK;
 }
 
+// Plan of the sub-line variant (Section 3.1.5): the window holds every
+// whole-chunk footprint (no per-half staging), and each of the 256 threads
+// owns a line of line_rows blended values in LDS.  A column's KZ slices reach
+// floor(v_max) - floor(v_min) + 2 <= ceil(|dv| (KZ - 1)) + 3 rows, with |dv| =
+// |m6| / w largest where w is smallest (at a corner column of the volume, w
+// being affine in i and j); one more row absorbs FP32 rounding.  Largest
+// slice count within the budget (76 KiB: two blocks per CU).
+fdk_status make_bp_plan_subline(const fdk_volume& vg, const fdk_stack& sg,
+                                const std::vector<IndexMatrix>& M, BpPlan& plan)
+{
+    (void)sg;
+    const int kz_force = env_int("FDK_BP_KZ", 0);
+    const int lds_budget = env_int("FDK_BP_SUBLINE_LDS_BUDGET", 76 * 1024);
+    double dv_max = 0.0;
+    for (const IndexMatrix& X : M) {
+        const double* m = X.m;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const double w = m[8] * (a ? vg.nx - 1 : 0) + m[9] * (b ? vg.ny - 1 : 0) + m[11];
+                dv_max = std::max(dv_max, std::fabs(m[6]) / w);
+            }
+    }
+    const int cands[3] = {32, 16, 8};
+    const int table_bytes = kViewBatch * kViewRec * 4;
+    for (int q = 0; q < 3; ++q) {
+        const int kz = cands[q];
+        if (kz_force && kz != kz_force) continue;
+        Extent e = footprint(vg, M, kz);
+        int pitch = 0;
+        for (int p = 0; p < kNumPitches; ++p)
+            if (kPitches[p] >= e.cols) { pitch = kPitches[p]; break; }
+        if (!pitch) continue;
+        const int line_rows = (int)std::ceil(dv_max * (kz - 1)) + 4;
+        const int64_t bytes = (int64_t)e.rows_full * pitch * 4 + (int64_t)line_rows * kThreads * 4 +
+                              table_bytes;
+        if (bytes > lds_budget && !(kz_force && bytes <= 150 * 1024)) continue;
+        plan.kz = kz;
+        plan.pitch = pitch;
+        plan.rows = e.rows_full;
+        plan.rows_full = e.rows_full;
+        plan.cols = e.cols;
+        plan.line_rows = line_rows;
+        plan.lds_bytes = bytes;
+        plan.ntx = (vg.nx + kTile - 1) / kTile;
+        plan.nty = (vg.ny + kTile - 1) / kTile;
+        plan.ntiles_pad = ((plan.ntx * plan.nty + 7) / 8) * 8;
+        plan.nchunks = (vg.nz + kz - 1) / kz;
+        plan.blocks = (int64_t)plan.ntiles_pad * plan.nchunks;
+        return FDK_OK;
+    }
+    return fail(FDK_E_UNSUPPORTED,
+                "the sub-line variant's window and lines do not fit in LDS for this geometry");
+}
+
 // v(i, j, k) + v(i, j, nz - 1 - k) = nh - 1 for all i, j, k iff, with
 // v w = m4 i + m5 j + m6 k + m7 and w = m8 i + m9 j + m11 (m10 = 0):
 // 2 m4 = (nh - 1) m8, 2 m5 = (nh - 1) m9, 2 m7 + (nz - 1) m6 = (nh - 1) m11.

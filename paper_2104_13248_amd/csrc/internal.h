@@ -47,6 +47,7 @@ struct BpPlan {
     int ntx = 0, nty = 0, ntiles_pad = 0, nchunks = 0;
     int64_t lds_bytes = 0;      // back-projector LDS per block
     int64_t blocks = 0;
+    int line_rows = 0;   // sub-line variant: rows of each thread's blended line
 };
 
 // Footprint-driven launch plan (cached by a hash of the inputs).
@@ -88,6 +89,11 @@ fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* strea
 fdk_status launch_backproject_sym(const BpLaunch& a, const BpPlan& plan, void* stream);
 fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
                             const std::vector<IndexMatrix>& M, BpPlan& plan);
+// Sub-line variant (whole volume, float32): a window that holds every
+// whole-chunk footprint plus one blended line per thread, and its launch.
+fdk_status make_bp_plan_subline(const fdk_volume& vg, const fdk_stack& sg,
+                                const std::vector<IndexMatrix>& M, BpPlan& plan);
+fdk_status launch_backproject_subline(const BpLaunch& a, const BpPlan& plan, void* stream);
 // Whether v(i, j, nz-1-k) = nh - 1 - v(i, j, k) for every view (index-space
 // matrices, relative tolerance 1e-10).
 bool bp_geometry_symmetric(const fdk_volume& vg, const fdk_stack& sg,

@@ -108,6 +108,48 @@ __global__ __launch_bounds__(kPT) void valu_fma_kernel(int iters, float* sink)
     if (s == -1.0f) sink[0] = s;
 }
 
+// One instruction of fdk_valu_op on chain register x (c, d: loop-invariant
+// operands).  Each form reads and writes x, so the 8 chains of a thread stay
+// independent and no instruction can be dropped or hoisted.
+template <int OP>
+__device__ __forceinline__ void valu_step(float& x, float c, unsigned d)
+{
+    if constexpr (OP == FDK_OP_FMA_F32) asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(x) : "v"(c));
+    else if constexpr (OP == FDK_OP_FMAC_F32) asm volatile("v_fmac_f32 %0, %1, %1" : "+v"(x) : "v"(c));
+    else if constexpr (OP == FDK_OP_SUB_F32) asm volatile("v_sub_f32 %0, %0, %1" : "+v"(x) : "v"(c));
+    else if constexpr (OP == FDK_OP_FRACT_F32) asm volatile("v_fract_f32 %0, %0" : "+v"(x));
+    else if constexpr (OP == FDK_OP_CVT_I32_F32) asm volatile("v_cvt_i32_f32 %0, %0" : "+v"(x));
+    else if constexpr (OP == FDK_OP_MAD_U32_U24) asm volatile("v_mad_u32_u24 %0, %0, %1, %1" : "+v"(x) : "v"(d));
+    else if constexpr (OP == FDK_OP_FMA_MIX_F32)
+        asm volatile("v_fma_mix_f32 %0, %1, %0, %0 op_sel_hi:[1,0,0]" : "+v"(x) : "v"(d));
+    else if constexpr (OP == FDK_OP_CVT_F32_F16) asm volatile("v_cvt_f32_f16 %0, %0" : "+v"(x));
+    else if constexpr (OP == FDK_OP_DOT2_F32_F16) asm volatile("v_dot2_f32_f16 %0, %1, %1, %0" : "+v"(x) : "v"(d));
+    else if constexpr (OP == FDK_OP_PK_FMA_F16) asm volatile("v_pk_fma_f16 %0, %0, %1, %1" : "+v"(x) : "v"(d));
+    else if constexpr (OP == FDK_OP_ADD_U32) asm volatile("v_add_u32 %0, %0, %1" : "+v"(x) : "v"(d));
+    else asm volatile("v_floor_f32 %0, %0" : "+v"(x));
+}
+
+template <int OP>
+__global__ __launch_bounds__(kPT) void valu_op_kernel(int iters, float* sink)
+{
+    float x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (float)(threadIdx.x + j) * 1e-3f;
+    const float c = 0.5f;
+    const unsigned d = 0x3c003c00u + threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) valu_step<OP>(x[j], c, d);
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s += x[j];
+    if (s == -1.0f) sink[0] = s;
+}
+
 // bytes a lane reads per LDS read instruction, and instructions per read
 // step (kReads steps per iteration)
 int64_t lds_bytes_per_lane_step(int pattern)
@@ -171,4 +213,23 @@ extern "C" fdk_status fdk_peak_valu_fma(int32_t blocks, int32_t iters, float* si
                        iters, sink);
     *ops_out = (int64_t)blocks * kPT * 8 * 16 * (int64_t)iters;
     return check_launch("FMA kernel");
+}
+
+extern "C" fdk_status fdk_peak_valu_op(int32_t op, int32_t blocks, int32_t iters, float* sink,
+                                       int64_t* ops_out, void* stream)
+{
+    if (!sink || !ops_out) return fail(FDK_E_INVALID, "sink/ops_out pointer is NULL");
+    if (blocks < 1 || iters < 1) return fail(FDK_E_INVALID, "blocks and iters must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    switch (op) {
+#define FDK_OP(m) case m: hipLaunchKernelGGL(valu_op_kernel<m>, dim3((unsigned)blocks), dim3(kPT), 0, st, iters, sink); break;
+        FDK_OP(FDK_OP_FMA_F32) FDK_OP(FDK_OP_FMAC_F32) FDK_OP(FDK_OP_SUB_F32)
+        FDK_OP(FDK_OP_FRACT_F32) FDK_OP(FDK_OP_CVT_I32_F32) FDK_OP(FDK_OP_MAD_U32_U24)
+        FDK_OP(FDK_OP_FMA_MIX_F32) FDK_OP(FDK_OP_CVT_F32_F16) FDK_OP(FDK_OP_DOT2_F32_F16)
+        FDK_OP(FDK_OP_PK_FMA_F16) FDK_OP(FDK_OP_ADD_U32) FDK_OP(FDK_OP_FLOOR_F32)
+#undef FDK_OP
+        default: return fail(FDK_E_INVALID, "unknown VALU instruction");
+    }
+    *ops_out = (int64_t)blocks * kPT * 8 * 16 * (int64_t)iters;
+    return check_launch("VALU instruction kernel");
 }

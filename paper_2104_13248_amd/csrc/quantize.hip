@@ -84,9 +84,13 @@ __global__ __launch_bounds__(kQThreads) void quantize_kernel(const float* __rest
     uint16_t* o = out + (size_t)s * npix;
     const int64_t t0 = (int64_t)blockIdx.x * kQThreads + threadIdx.x;
     const int64_t nthreads = (int64_t)gridDim.x * kQThreads;
-    // v_cvt_f16_f32: round to nearest even
+    // product, then v_cvt_f16_f32 (round to nearest even).  The empty asm
+    // keeps the two apart: fused into one mixed-precision FMA with a +0
+    // addend they would turn a -0 product into +0.
     auto half_bits = [inv](float x) {
-        return (unsigned)__builtin_bit_cast(uint16_t, (_Float16)(x * inv));
+        float p = x * inv;
+        asm volatile("" : "+v"(p));
+        return (unsigned)__builtin_bit_cast(uint16_t, (_Float16)p);
     };
     int64_t head = 0;
     if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {

@@ -104,7 +104,7 @@ fdk_status upload_async(const void* host, size_t bytes, void* stream, void** dev
 
 extern "C" const char* fdk_last_error(void) { return fdk::t_last_error.c_str(); }
 
-extern "C" const char* fdk_status_string(fdk_status s)
+extern "C" const char* fdk_status_string(int32_t s)
 {
     switch (s) {
         case FDK_OK: return "ok";

@@ -126,6 +126,7 @@ def test_quantizer_bit_exact():
     proj = proj.copy()
     proj[3] = 0.0                                   # an all-zero view
     proj[5] *= np.float32(1e-20)                    # tiny values (binary16 subnormals)
+    proj[7, 0, :] = np.float32(-0.0)                # negative zeros keep their sign
     h_ref, s_ref = oracle.quantize_f16(proj)
     h, s = fdk.quantize_f16(torch.from_numpy(proj).cuda())
     torch.cuda.synchronize()

@@ -105,6 +105,30 @@ fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k
                                 float* vol_slab, const fdk_stack* sg, const void* proj,
                                 const float* scale, const double* mats, void* stream);
 
+/* Views per call of fdk_backproject_noalloc (the size of its fixed scratch array). */
+#define FDK_NOALLOC_MAX_VIEWS 16384
+
+/*
+ * fdk_backproject_noalloc -- fdk_backproject for callers that cannot allocate
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, semantics and errors as fdk_backproject
+ * and a bitwise identical result, but the call makes no device, pinned-host or
+ * stream-ordered allocation.  Its only scratch -- the world matrices and their
+ * FP64 compositions with the voxel grid, 192 bytes per view -- is a fixed
+ * device array for FDK_NOALLOC_MAX_VIEWS views (3 MiB), one per GPU, held
+ * until the process ends; a stack of more views gives FDK_E_UNSUPPORTED
+ * before any HIP call.  The matrices reach that array as kernel arguments (32
+ * views per launch), so `mats` may be reused as soon as the call returns.
+ * Nothing in the array needs to start at zero: each call writes the entries
+ * it reads.  All calls on one GPU share the array: calls that overlap in time
+ * on one GPU (on different streams, or from several host threads) race and
+ * must be serialised by the caller; calls on one stream are ordered.
+ */
+fdk_status fdk_backproject_noalloc(const fdk_volume* vg, float* vol,
+                                   const fdk_stack* sg, const void* proj,
+                                   const float* scale, const double* mats,
+                                   void* stream);
+
 /*
  * fdk_forwardproject -- proj += A vol, the exact transpose of the back-projection
  * (the projector of the iterative methods of Section 1: the adjoint pair

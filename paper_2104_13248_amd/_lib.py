@@ -54,6 +54,7 @@ def _load():
     sigs = {
         "fdk_backproject": [VP, P, SP, P, P, P, P],
         "fdk_backproject_slab": [VP, I, I, P, SP, P, P, P, P],
+        "fdk_backproject_noalloc": [VP, P, SP, P, P, P, P],
         "fdk_forwardproject": [VP, P, SP, P, P, P],
         "fdk_filter": [SP, P, I, P, P, D, D, D, D, D, D, D, I, P],
         "fdk_quantize_f16": [I, I, I, P, P, P, P],
@@ -89,7 +90,7 @@ def _load():
 lib = _load()
 
 #: names declared in include/fdk.h, include/fdk_learn.h and include/fdk_ablation.h
-EXPORTS = ("fdk_backproject", "fdk_backproject_slab",
+EXPORTS = ("fdk_backproject", "fdk_backproject_slab", "fdk_backproject_noalloc",
            "fdk_forwardproject", "fdk_filter",
            "fdk_quantize_f16", "fdk_circular_matrices", "fdk_phantom_project", "fdk_bp_plan",
            "fdk_last_error", "fdk_status_string",

@@ -34,7 +34,7 @@ DEVICE = ["-x", "hip", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-op
 
 SOURCES = ["api.cpp", "geometry.cpp", "runtime.cpp", "compose.hip", "bp.hip", "fp.hip",
            "filter.hip", "quantize.hip", "phantom.hip", "learn.hip",
-           "ablation.hip", "peaks.hip"]
+           "ablation.hip", "peaks.hip", "noalloc.hip"]
 HEADERS = ["internal.h", "footprint.h"]
 
 

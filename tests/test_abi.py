@@ -177,6 +177,19 @@ def test_filter_quantize_phantom_validation():
                                  None) == E_INVALID             # zero semi-axis
 
 
+def test_noalloc_rejects_more_views_than_its_scratch():
+    vg, _, _ = _geom(C1)
+    big = 16385
+    sg = _lib.stack_struct(big, C1["nh"], C1["nw"])
+    m = np.zeros((big, 3, 4))
+    assert _lib.lib.fdk_backproject_noalloc(ctypes.byref(vg), FAKE, ctypes.byref(sg), FAKE, None,
+                                            _lib.ptr(m), None) == E_UNSUPPORTED
+    assert b"16384" in _lib.lib.fdk_last_error()
+    vg2, sg2, m2 = _geom(C1)
+    assert _lib.lib.fdk_backproject_noalloc(ctypes.byref(vg2), None, ctypes.byref(sg2), FAKE,
+                                            None, _lib.ptr(m2), None) == E_INVALID
+
+
 def test_peak_microbenchmarks_validate():
     L = _lib.lib
     n = ctypes.c_int64(0)

@@ -43,8 +43,11 @@ typedef enum {
                                of rows floor(v) and floor(v) + 1 (36-word rows) at the columns
                                of a 16 x 16 voxel tile seen at 1.6 detector pixels per voxel
                                (view at 30 degrees), v advancing 1.6 rows per slice */
-    FDK_LDS_TAPS_F32 = 5    /* the same with float32 taps: per update, words (c, c + 1) of
+    FDK_LDS_TAPS_F32 = 5,   /* the same with float32 taps: per update, words (c, c + 1) of
                                rows floor(v) and floor(v) + 1 (72-word rows) */
+    FDK_LDS_B64_ASM = 6,    /* ds_read_b64 at 8-byte aligned addresses, issued four at a time
+                               by an assembly block that waits for them */
+    FDK_LDS_B64_ASM_DWORD = 7 /* the same at addresses 4 mod 8 (dword aligned) */
 } fdk_lds_pattern;
 
 /*

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(kPT) void lds_read_kernel(int iters, const LdsSteps
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     typedef __attribute__((address_space(3))) volatile u32x2 lds_vu64;
     lds_vu32* vbuf = (lds_vu32*)(size_t)(__attribute__((address_space(3))) unsigned*)buf;
+    const unsigned lds_base = (unsigned)(size_t)(__attribute__((address_space(3))) unsigned*)buf;
     for (int i = threadIdx.x; i < kLdsWords; i += kPT) buf[i] = (unsigned)i * 2654435761u + blockIdx.x;
     __syncthreads();
     const int tid = threadIdx.x, lane = tid & 63;
@@ -75,6 +76,25 @@ __global__ __launch_bounds__(kPT) void lds_read_kernel(int iters, const LdsSteps
                 const uint4 x = reinterpret_cast<const uint4*>(buf)[lane + 64 * q];
                 a ^= x.x ^ x.y;
                 b ^= x.z ^ x.w;
+            } else if constexpr (MODE == FDK_LDS_B64_ASM || MODE == FDK_LDS_B64_ASM_DWORD) {
+                // four reads in flight, waited for inside the same block; steps
+                // q = 0, 4, 8, 12 issue them (the others do nothing)
+                if ((q & 3) == 0) {
+                    const unsigned addr = lds_base + 8u * (unsigned)lane + 2048u * (unsigned)(q >> 2) +
+                                          (MODE == FDK_LDS_B64_ASM_DWORD ? 4u : 0u);
+                    u32x2 r0, r1, r2, r3;
+                    asm volatile(
+                        "ds_read_b64 %0, %4\n"
+                        "ds_read_b64 %1, %4 offset:512\n"
+                        "ds_read_b64 %2, %4 offset:1024\n"
+                        "ds_read_b64 %3, %4 offset:1536\n"
+                        "s_waitcnt lgkmcnt(0)"
+                        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+                        : "v"(addr)
+                        : "memory");
+                    a ^= r0.x ^ r1.x ^ r2.x ^ r3.x;
+                    b ^= r0.y ^ r1.y ^ r2.y ^ r3.y;
+                }
             } else if constexpr (MODE == FDK_LDS_TAPS_F16) {
                 const int w = S.off[q] * 36 + col;
                 a ^= buf[w];
@@ -161,6 +181,8 @@ int64_t lds_bytes_per_lane_step(int pattern)
         case FDK_LDS_B128: return 16;
         case FDK_LDS_TAPS_F16: return 8;
         case FDK_LDS_TAPS_F32: return 16;
+        case FDK_LDS_B64_ASM: return 8;          // 16 reads per iteration in blocks of four
+        case FDK_LDS_B64_ASM_DWORD: return 8;
     }
     return 0;
 }
@@ -198,6 +220,7 @@ extern "C" fdk_status fdk_peak_lds_read(int32_t pattern, int32_t blocks, int32_t
 #define FDK_LDS(m) case m: hipLaunchKernelGGL(lds_read_kernel<m>, dim3((unsigned)blocks), dim3(kPT), 0, st, iters, S, sink); break;
         FDK_LDS(FDK_LDS_B32) FDK_LDS(FDK_LDS_READ2_B32) FDK_LDS(FDK_LDS_B64)
         FDK_LDS(FDK_LDS_B128) FDK_LDS(FDK_LDS_TAPS_F16) FDK_LDS(FDK_LDS_TAPS_F32)
+        FDK_LDS(FDK_LDS_B64_ASM) FDK_LDS(FDK_LDS_B64_ASM_DWORD)
 #undef FDK_LDS
     }
     *bytes_out = (int64_t)blocks * kPT * (int64_t)iters * kReads * per;

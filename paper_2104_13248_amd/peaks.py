@@ -8,7 +8,8 @@ import torch
 
 from ._lib import check, lib
 
-LDS_PATTERNS = {"b32": 0, "read2_b32": 1, "b64": 2, "b128": 3, "taps_f16": 4, "taps_f32": 5}
+LDS_PATTERNS = {"b32": 0, "read2_b32": 1, "b64": 2, "b128": 3, "taps_f16": 4, "taps_f32": 5,
+                "b64_asm": 6, "b64_asm_dword": 7}
 VALU_OPS = {"v_fma_f32": 0, "v_fmac_f32": 1, "v_sub_f32": 2, "v_fract_f32": 3,
             "v_cvt_i32_f32": 4, "v_mad_u32_u24": 5, "v_fma_mix_f32": 6, "v_cvt_f32_f16": 7,
             "v_dot2_f32_f16": 8, "v_pk_fma_f16": 9, "v_add_u32": 10, "v_floor_f32": 11}

@@ -197,7 +197,9 @@ def test_peak_microbenchmarks_validate():
     assert L.fdk_peak_hbm_read(FAKE, 1000, 8, FAKE, None) == E_INVALID          # not 16 * k
     assert L.fdk_peak_hbm_read(ctypes.c_void_p(0x10004), 1024, 8, FAKE, None) == E_INVALID
     assert L.fdk_peak_hbm_read(FAKE, 1024, 0, FAKE, None) == E_INVALID
-    assert L.fdk_peak_lds_read(6, 8, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_lds_read(8, 8, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_valu_op(12, 8, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
+    assert L.fdk_peak_valu_op(0, 8, 0, FAKE, ctypes.addressof(n), None) == E_INVALID
     assert L.fdk_peak_lds_read(0, 0, 1, FAKE, ctypes.addressof(n), None) == E_INVALID
     assert L.fdk_peak_lds_read(0, 8, 1, None, ctypes.addressof(n), None) == E_INVALID
     assert L.fdk_peak_valu_fma(8, 0, FAKE, ctypes.addressof(n), None) == E_INVALID

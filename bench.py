@@ -156,9 +156,9 @@ def accuracy_and_oracle(cfg, mats, filt, h, sc, vol32, vol16):
         w16 = ow.cut_windows_device(h, origin, wr, wc)
         t = time.perf_counter()
         ref32 = oracle.backproject_block(w32, mats, shape, voxel, box, origin=origin,
-                                         detector=(nh, nw))
+                                         detector=(nh, nw), threads=threads)
         ref16 = oracle.backproject_block(w16, mats, shape, voxel, box, scale=sc_h,
-                                         origin=origin, detector=(nh, nw))
+                                         origin=origin, detector=(nh, nw), threads=threads)
         t_oracle += time.perf_counter() - t
         n_oracle += 2 * ref32.size * npv
         g32 = vol32[k0:k1, j0:j1, i0:i1].double().cpu().numpy()
@@ -169,8 +169,9 @@ def accuracy_and_oracle(cfg, mats, filt, h, sc, vol32, vol16):
         acc["e16d"] += float(((g16 - ref16) ** 2).sum())
         acc["r16"] += float((ref16 ** 2).sum())
         if q == 0:
-            # one thread, the first 128 views of the centre block
-            nv = min(128, npv)
+            # one thread, the first 256 views of the centre block (the
+            # thread count is passed explicitly to every call)
+            nv = min(256, npv)
             t = time.perf_counter()
             oracle.backproject_block(w32[:nv], mats[:nv], shape, voxel, box, origin=origin[:nv],
                                      detector=(nh, nw), threads=1)
@@ -192,7 +193,7 @@ def accuracy_and_oracle(cfg, mats, filt, h, sc, vol32, vol16):
                      "window only; %.1f s" % (npv, t_oracle),
            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
            "single_core_gups": single,
-           "single_core_sample": "centre 64^3 block, first %d views, 1 thread" % min(128, npv)}
+           "single_core_sample": "centre 64^3 block, first %d views, 1 thread" % min(256, npv)}
     return rel, cpu
 
 

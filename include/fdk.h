@@ -86,6 +86,10 @@ typedef struct fdk_stack {
  * is parallel to the rotation axis), and w must be positive over the volume.
  * Otherwise FDK_E_GEOMETRY.  vol and proj must not overlap.
  * The result is deterministic: no atomics, fixed summation order.
+ * Each view's detector footprint of a block of voxels is staged in LDS; where
+ * it cannot be (strong magnification: roughly beyond 15 detector pixels per
+ * voxel) the taps are read from memory instead, with the same result
+ * contract (fdk_bp_plan reports lds_pitch = 0 for such launches).
  */
 fdk_status fdk_backproject(const fdk_volume* vg, float* vol,
                            const fdk_stack* sg, const void* proj,
@@ -232,7 +236,8 @@ fdk_status fdk_phantom_project(const double* ell, int32_t n_ell, const fdk_stack
  * these inputs: out[0..11] = tile_x, tile_y, kz (slices per thread),
  * lds_pitch (words per LDS row), lds_rows, lds_bytes per block, blocks,
  * threads per block, rows_full (rows of the tallest whole-chunk footprint;
- * taller than lds_rows means such footprints are staged per half-chunk),
+ * taller than lds_rows means such footprints are staged per half-chunk;
+ * lds_pitch = lds_rows = lds_bytes = 0: the taps are read from memory),
  * then the forward projector's lds_bytes per block, detector rows per band
  * and detector columns per chunk.  The tile depends on sg->dtype (binary16
  * tiles hold two regions of pair words).  out: host int64 [12].  Validates

@@ -12,7 +12,10 @@
  *   FDK_VARIANT_GLOBAL_TAPS  production structure (hoisting, register
  *                            accumulation over all views) with the bilinear
  *                            taps read from global memory instead of a
- *                            staged LDS window (Section 3.2 removed); nb is
+ *                            staged LDS window (Section 3.2 removed): the
+ *                            library's direct organisation, which
+ *                            fdk_backproject itself uses when a block's
+ *                            footprint does not fit an LDS tile; nb is
  *                            ignored.
  *   FDK_VARIANT_LISTING1     Listing 1 on the GPU: a thread per voxel, the
  *                            full projection per (voxel, view) (no hoisting,

@@ -114,8 +114,9 @@ def sweep(config: str = "c2", views: int | None = None, nbs=(1, 2, 4, 8, 16, 32,
 
 
 def compare_problem(name: str, reps: int = 2, out=sys.stdout):
-    """Production against the sub-line and symmetric organisations on one of
-    the paper's problem sizes (Table 3; geometry reading of problems.py)."""
+    """Production against the sub-line, symmetric and global-taps
+    organisations on one of the paper's problem sizes (Table 3; geometry
+    reading of problems.py)."""
     from . import problems
     shape, voxel, mats, nh, nw = problems.geometry(name)
     npv = problems.VIEWS
@@ -125,7 +126,7 @@ def compare_problem(name: str, reps: int = 2, out=sys.stdout):
     vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
     n_upd = vol.numel() * npv
     rows = []
-    for variant in ("production", "subline", "symmetry"):
+    for variant in ("production", "subline", "symmetry", "global_taps"):
         fn = (lambda: backproject(vol, proj, mats, voxel)) if variant == "production" else \
             (lambda: backproject_variant(vol, proj, mats, voxel, variant))
         r = {"problem": name, "detector": nh, "volume": shape[0], "views": npv,
@@ -145,8 +146,8 @@ def main(argv=None):
     ap.add_argument("--config", default="c2")
     ap.add_argument("--views", type=int, default=None, help="views (default: the workload's)")
     ap.add_argument("--problem", default=None,
-                    help="comma-separated problems of Table 3 (P1..P10): production, sub-line "
-                         "and symmetric organisations only")
+                    help="comma-separated problems of Table 3 (P1..P10): production, sub-line, "
+                         "symmetric and global-taps organisations only")
     ap.add_argument("--reps", type=int, default=2)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)

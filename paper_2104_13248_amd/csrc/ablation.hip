@@ -10,15 +10,15 @@
 //                    volume read and written once per launch of nb views
 //                    (Section 3.1.3's batch size nb; the host launches np / nb
 //                    times).
-//   global_kernel    the production kernel's structure (16 x 16 columns x KZ
-//                    slices per block, u, w and 1/w^2 hoisted per column and
-//                    view, all views accumulated in registers) but with the
-//                    taps read from global memory instead of an LDS window
-//                    (Section 3.2's local-memory staging removed).
+//
+// (The global-taps variant -- the production structure with Section 3.2's
+// local-memory staging removed -- is the production library's own direct
+// organisation, bp_direct_kernel, which also serves strongly magnified
+// geometries.)
 //
 // The projection of a voxel is evaluated in FP64 (the MI355X vector FP64 rate
-// equals its non-packed FP32 rate) and reduced to FP32 offsets below the
-// integer part, so both kernels meet the FP32 tolerance against the oracle.
+// equals its slow-class FP32 rate) and reduced to FP32 offsets below the
+// integer part, so the kernel meets the FP32 tolerance against the oracle.
 #include <hip/hip_runtime.h>
 
 #include "fdk_ablation.h"
@@ -74,45 +74,6 @@ __global__ __launch_bounds__(256) void listing1_kernel(const AblArgs A)
     A.vol[q] += acc;
 }
 
-template <int KZ>
-__global__ __launch_bounds__(256) void global_kernel(const AblArgs A)
-{
-    const int ntx = (A.nx + 15) / 16, nty = (A.ny + 15) / 16;
-    const int tile = blockIdx.x % (ntx * nty), chunk = blockIdx.x / (ntx * nty);
-    const int i = (tile % ntx) * 16 + (threadIdx.x & 15);
-    const int j = (tile / ntx) * 16 + (threadIdx.x >> 4);
-    const int kc = chunk * KZ;
-    if (i >= A.nx || j >= A.ny) return;                      // no barriers in this kernel
-    const double di = i, dj = j;
-    float acc[KZ];
-#pragma unroll
-    for (int t = 0; t < KZ; ++t) acc[t] = 0.f;
-    for (int s = A.s0; s < A.s1; ++s) {
-        const double* m = A.M + 12 * (size_t)s;
-        // hoisted per (column, view): u and w do not depend on k
-        const double w = m[8] * di + m[9] * dj + m[11];
-        const double rw = 1.0 / w;
-        const double u = (m[0] * di + m[1] * dj + m[3]) * rw;
-        const double v0 = (m[4] * di + m[5] * dj + m[6] * kc + m[7]) * rw;
-        const double fu_d = floor(u), fv0 = floor(v0);
-        const float fu = (float)(u - fu_d), W = (float)(rw * rw);
-        const int c = (int)fu_d, r0 = (int)fv0;
-        const float vl = (float)(v0 - fv0), dv = (float)(m[6] * rw);
-        const float* p = A.proj + (size_t)s * A.nh * A.nw;
-#pragma unroll
-        for (int t = 0; t < KZ; ++t) {
-            const float v = fmaf((float)t, dv, vl);          // row offset from r0
-            const float fl = floorf(v);
-            acc[t] = fmaf(W, bilinear(p, r0 + (int)fl, c, v - fl, fu, A.nh, A.nw), acc[t]);
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < KZ; ++t) {
-        const int k = kc + t;
-        if (k < A.nz) A.vol[((size_t)k * A.ny + j) * A.nx + i] += acc[t];
-    }
-}
-
 }  // namespace
 
 fdk_status launch_backproject_variant(int variant, int nb, const float* proj,
@@ -137,16 +98,6 @@ fdk_status launch_backproject_variant(int variant, int nb, const float* proj,
             if (s != FDK_OK) return s;
         }
         return FDK_OK;
-    }
-    if (variant == FDK_VARIANT_GLOBAL_TAPS) {
-        constexpr int KZ = 32;
-        const int64_t tiles = (int64_t)((nx + 15) / 16) * ((ny + 15) / 16);
-        const int64_t blocks = tiles * ((nz + KZ - 1) / KZ);
-        if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "volume too large for one launch");
-        A.s0 = 0;
-        A.s1 = np;
-        hipLaunchKernelGGL(global_kernel<KZ>, dim3((unsigned)blocks), dim3(256), 0, st, A);
-        return check_launch("global-taps back-projection kernel");
     }
     return fail(FDK_E_INVALID, "unknown back-projection variant");
 }

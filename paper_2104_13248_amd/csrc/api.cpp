@@ -59,9 +59,13 @@ extern "C" fdk_status fdk_bp_plan(const fdk_volume* vg, const fdk_stack* sg, con
     return FDK_OK;
 }
 
-extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k_count,
-                                           float* vol_slab, const fdk_stack* sg, const void* proj,
-                                           const float* scale, const double* mats, void* stream)
+namespace {
+
+// The back-projection of fdk_backproject_slab; `direct` forces the direct
+// organisation (taps from memory) whatever the footprint.
+fdk_status backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k_count,
+                            float* vol_slab, const fdk_stack* sg, const void* proj,
+                            const float* scale, const double* mats, void* stream, bool direct)
 {
     std::vector<IndexMatrix> M;
     fdk_status s = common_checks(vg, sg, true, mats, &M);
@@ -79,6 +83,12 @@ extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin
     BpPlan plan;
     s = make_bp_plan(*vg, *sg, M, plan);
     if (s != FDK_OK) return s;
+    if (direct && !plan.direct) {
+        plan.direct = true;
+        plan.kz = 32;
+        plan.nchunks = (vg->nz + plan.kz - 1) / plan.kz;
+        plan.blocks = (int64_t)plan.ntiles_pad * plan.nchunks;
+    }
 
     const size_t mbytes = (size_t)sg->np * 12 * sizeof(double);
     void* d_world = nullptr;
@@ -108,6 +118,15 @@ extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin
     fdk_status s3 = device_free_async(d_world, stream);
     if (s != FDK_OK) return s;
     return s2 != FDK_OK ? s2 : s3;
+}
+
+}  // namespace
+
+extern "C" fdk_status fdk_backproject_slab(const fdk_volume* vg, int32_t k_begin, int32_t k_count,
+                                           float* vol_slab, const fdk_stack* sg, const void* proj,
+                                           const float* scale, const double* mats, void* stream)
+{
+    return backproject_slab(vg, k_begin, k_count, vol_slab, sg, proj, scale, mats, stream, false);
 }
 
 extern "C" fdk_status fdk_backproject(const fdk_volume* vg, float* vol, const fdk_stack* sg,
@@ -415,6 +434,8 @@ extern "C" fdk_status fdk_backproject_variant(int32_t variant, int32_t nb, const
             }
         return s != FDK_OK ? s : s2;
     }
+    if (variant == FDK_VARIANT_GLOBAL_TAPS)
+        return backproject_slab(vg, 0, vg->nz, vol, sg, proj, nullptr, mats, stream, true);
     if (variant == FDK_VARIANT_PRODUCTION) {
         const size_t view = (size_t)sg->nh * sg->nw;
         for (int32_t s0 = 0; s0 < sg->np; s0 += batch) {

@@ -593,6 +593,85 @@ __global__ __launch_bounds__(kThreads) void bp_subline_kernel(const BpArgs A, in
     }
 }
 
+// Direct organisation, for geometries whose block footprint does not fit an
+// LDS tile (strong magnification: beyond ~15 detector pixels per voxel, a
+// 16 x 16 x 8 block reaches more pixels than the widest tile holds): the same
+// blocks, hoisting and register accumulation, with the four taps read from
+// the projection in memory through the caches.  Per (column, view) the
+// projection of the column is evaluated in FP64 and reduced to an integer
+// row/column origin plus FP32 offsets below one pixel; the row step per
+// slice is split into its integer part (added as an integer) and its
+// fraction (accumulated in FP32), so that at tens of rows per slice the FP32
+// row coordinate of the last slice is still accurate to ~1e-6 of a pixel.
+// Taps outside the detector read as zero.
+template <bool F16>
+__device__ __forceinline__ float direct_tap(const void* view, int r, int c, int nh, int nw)
+{
+    if ((unsigned)r >= (unsigned)nh || (unsigned)c >= (unsigned)nw) return 0.f;
+    const size_t q = (size_t)r * nw + c;
+    if (F16) return (float)__builtin_bit_cast(_Float16, reinterpret_cast<const uint16_t*>(view)[q]);
+    return reinterpret_cast<const float*>(view)[q];
+}
+
+template <int KZ, bool F16>
+__global__ __launch_bounds__(kThreads) void bp_direct_kernel(const BpArgs A)
+{
+    const BlockPos bp = block_position(blockIdx.x, A.ntiles_pad);
+    const int t_id = bp.tile;
+    if (t_id >= A.ntiles) return;                             // padding block (no barriers here)
+    const int tx = t_id % A.ntx, ty = t_id / A.ntx;
+    const int kc = (A.chunk_first + bp.chunk_local) * KZ;
+    const int i = tx * kTile + (threadIdx.x & (kTile - 1));
+    const int j = ty * kTile + (threadIdx.x >> 4);
+    if (i >= A.nx || j >= A.ny) return;
+    const double di = i, dj = j;
+    const size_t view_elems = (size_t)A.nh * A.nw;
+    const char* proj = reinterpret_cast<const char*>(A.proj);
+    // pixel offsets are clamped to this range before conversion: everything
+    // beyond it is off any detector of fewer than 2^24 rows or columns
+    constexpr double kFar = 16777216.0;
+
+    float acc[KZ];
+#pragma unroll
+    for (int t = 0; t < KZ; ++t) acc[t] = 0.f;
+    for (int s = 0; s < A.np; ++s) {
+        const double* m = A.M + 12 * (size_t)s;
+        const double rw = 1.0 / (m[8] * di + m[9] * dj + m[11]);
+        const double u = (m[0] * di + m[1] * dj + m[3]) * rw;
+        const double v0 = (m[4] * di + m[5] * dj + m[6] * (double)kc + m[7]) * rw;
+        const double cu = fmin(fmax(floor(u), -kFar), kFar);
+        const double r0d = fmin(fmax(floor(v0), -kFar), kFar);
+        const float fu = (float)(u - floor(u));
+        const float vl = (float)(v0 - r0d);                   // v of slice kc relative to row r0
+        const double dvd = m[6] * rw;                         // rows per slice
+        const double dvi_d = fmin(fmax(floor(dvd), -1048576.0), 1048576.0);
+        const float dvf = (float)(dvd - floor(dvd));          // its fraction, in [0, 1)
+        const int dvi = (int)dvi_d;                           // and its integer part
+        const float W = (float)(rw * rw) * (A.scale ? A.scale[s] : 1.0f);
+        const int c = (int)cu, r0 = (int)r0d;
+        const void* view = proj + (size_t)s * view_elems * (F16 ? 2 : 4);
+#pragma unroll
+        for (int t = 0; t < KZ; ++t) {
+            const float v = fmaf((float)t, dvf, vl);            // < KZ + 1
+            const float fl = floorf(v);
+            const float fv = v - fl;
+            const int r = r0 + t * dvi + (int)fl;
+            const float p00 = direct_tap<F16>(view, r, c, A.nh, A.nw);
+            const float p01 = direct_tap<F16>(view, r, c + 1, A.nh, A.nw);
+            const float p10 = direct_tap<F16>(view, r + 1, c, A.nh, A.nw);
+            const float p11 = direct_tap<F16>(view, r + 1, c + 1, A.nh, A.nw);
+            const float h0 = fmaf(fu, p01 - p00, p00), h1 = fmaf(fu, p11 - p10, p10);
+            acc[t] = fmaf(W, fmaf(fv, h1 - h0, h0), acc[t]);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < KZ; ++t) {
+        const int k = kc + t;
+        if (k >= A.k_begin && k < A.k_end)
+            A.vol[((size_t)(k - A.k_begin) * A.ny + j) * A.nx + i] += acc[t];
+    }
+}
+
 // Four waves per SIMD: the register budget that, with the LDS tile of the
 // launch plan, keeps four or more blocks resident per CU.
 template <int KZ, int PITCH, bool F16>
@@ -831,6 +910,21 @@ fdk_status launch_backproject(const BpLaunch& a, const BpPlan& plan, void* strea
     const size_t lds = (size_t)plan.lds_bytes;
     const int64_t blocks = (int64_t)plan.ntiles_pad * nch;
     if (blocks >= (1ll << 31)) return fail(FDK_E_UNSUPPORTED, "grid too large");
+    if (plan.direct) {
+#define FDK_DIRECT(KZ_)                                                                          \
+        if (a.f16)                                                                               \
+            hipLaunchKernelGGL((bp_direct_kernel<KZ_, true>), dim3((unsigned)blocks), dim3(kThreads), 0, st, A); \
+        else                                                                                     \
+            hipLaunchKernelGGL((bp_direct_kernel<KZ_, false>), dim3((unsigned)blocks), dim3(kThreads), 0, st, A); \
+        return check_launch("direct back-projection kernel");
+        switch (plan.kz) {
+            case 8: { FDK_DIRECT(8) }
+            case 16: { FDK_DIRECT(16) }
+            case 32: { FDK_DIRECT(32) }
+        }
+#undef FDK_DIRECT
+        return fail(FDK_E_UNSUPPORTED, "no kernel for this slice count");
+    }
     switch (plan.kz) {
         case 8: return launch_kz<8>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);
         case 16: return launch_kz<16>(A, plan.pitch, a.f16, lds, (unsigned)blocks, st);

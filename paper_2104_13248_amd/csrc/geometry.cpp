@@ -230,12 +230,14 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
     const int kz_force = env_int("FDK_BP_KZ", 0);
     const int lds_budget = env_int("FDK_BP_LDS_BUDGET", 32 * 1024);
     const int tile_bytes = env_int("FDK_BP_TILE_BYTES", 39 * 1024);
+    const int direct_force = env_int("FDK_BP_DIRECT", 0);
     uint64_t h = 1469598103934665603ull;
     h = fnv1a(h, &vg.nx, sizeof(int32_t) * 3);
     h = fnv1a(h, &sg.np, sizeof(int32_t) * 4);   // np, nh, nw, dtype
     h = fnv1a(h, &kz_force, sizeof(int));
     h = fnv1a(h, &lds_budget, sizeof(int));
     h = fnv1a(h, &tile_bytes, sizeof(int));
+    h = fnv1a(h, &direct_force, sizeof(int));
     h = fnv1a(h, M.data(), M.size() * sizeof(IndexMatrix));
     {
         std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -277,10 +279,14 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
         }
         if (found && best_bytes <= lds_budget) break;
     }
-    if (!found)
-        return fail(FDK_E_UNSUPPORTED,
-                    "projection footprint of a 16x16x8 voxel block does not fit in LDS "
-                    "(magnification too large for the detector pitch)");
+    if (!found || direct_force) {
+        // Strong magnification (a 16 x 16 x 8 block's footprint wider than the
+        // widest LDS pitch, or taller than 150 KiB of rows): the direct
+        // organisation, same blocks and hoisting, taps read from memory.
+        best = BpPlan();
+        best.kz = kz_force ? kz_force : 32;
+        best.direct = true;
+    }
     // Rows beyond that cost no occupancy while four blocks (the register
     // limit: four waves per SIMD) still share a CU's 160 KiB of LDS: take as
     // many as fit, so that fewer footprints are staged per half-chunk.  A
@@ -289,7 +295,7 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
     // banks (mod 32) after the first for every pitch, so lanes reading
     // neighbouring even and odd pairs do not meet in one bank (an offset of
     // 0 mod 32 measured 4-5% slower).
-    {
+    if (!best.direct) {
         const int fit = (tile_bytes - table_bytes) / (best.pitch * 4);
         int r = std::min(fit, best.rows_full);
         if (sg.dtype == FDK_F16) {

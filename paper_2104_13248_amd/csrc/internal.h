@@ -48,6 +48,7 @@ struct BpPlan {
     int64_t lds_bytes = 0;      // back-projector LDS per block
     int64_t blocks = 0;
     int line_rows = 0;   // sub-line variant: rows of each thread's blended line
+    bool direct = false; // taps read from memory (footprint too large for an LDS tile)
 };
 
 // Footprint-driven launch plan (cached by a hash of the inputs).

@@ -140,7 +140,11 @@ def main(argv=None):
         f, meta = LearnedFilter.load(a.checkpoint, dev)
         start = int(meta.get("next", 0))
     else:
-        std = float(torch.cat([cosine_weight(r, data.scan).flatten()[::97] for r, _ in held]).std())
+        # input normalisation from training phantoms only (the held-out set is
+        # used by evaluate() alone)
+        first = [data.pair(i)[0] for i in range(min(4, a.phantoms))]
+        std = float(torch.cat([cosine_weight(r, data.scan).flatten()[::97] for r in first]).std())
+        del first
         f = LearnedFilter(dev, residual=not a.replace, seed=a.seed, input_std=std)
 
     base = evaluate(f, data, held)

@@ -355,3 +355,71 @@ def test_split_footprints(case, kz, monkeypatch):
         fdk.backproject_slab(slab, shape, k0, p, mats, voxel)
         torch.cuda.synchronize()
         assert np.array_equal(slab.cpu().numpy().view(np.uint32), got[k0:k0 + kc].view(np.uint32))
+
+
+# Strong magnification: a 16 x 16 x 8 block's footprint is wider than the
+# widest LDS tile, so the library reads the taps from memory (the plan
+# reports lds_pitch 0).  Up to ~20 detector pixels per voxel near the centre.
+MAGNIFIED = [
+    # scan overrides, volume shape, voxel, (np, nh, nw)
+    (dict(sod=60.0, sdd=240.0, du=0.2, dv=0.2), (20, 20, 24), 1.0, (16, 420, 460)),
+    (dict(sod=90.0, sdd=900.0, du=0.5, dv=0.5, theta0=0.4, u_off=3.0), (9, 14, 11), 1.0, (12, 500, 480)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(MAGNIFIED)))
+def test_strong_magnification_direct_taps(case):
+    over, shape, vox, (npv, nh, nw) = MAGNIFIED[case]
+    scan = dict(wl.CONFIGS["c1"]["scan"], **over)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    voxel = (vox, vox, vox)
+    plan = fdk.bp_plan(shape, voxel, npv, nh, nw, mats)
+    log("magnified case", case, plan)
+    assert plan["lds_pitch"] == 0
+    proj = wl.gaussian(1300 + case, (npv, nh, nw))
+    ref = oracle.backproject(proj, mats, shape, voxel)
+    got = gpu_bp(proj, mats, shape, voxel)
+    e = rel(got, ref)
+    log("f32 rel-L2", e)
+    assert e <= TOL32
+    h, s = fdk.quantize_f16(torch.from_numpy(proj).cuda())
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, voxel, scale=s)
+    torch.cuda.synchronize()
+    ref16 = oracle.backproject(h.cpu().numpy(), mats, shape, voxel, scale=s.cpu().numpy())
+    e16 = rel(vol.cpu().numpy(), ref16)
+    log("f16 rel-L2 vs dequantised", e16)
+    assert e16 <= TOL32
+
+
+@pytest.mark.parametrize("kz", [0, 8, 16])
+def test_direct_organisation_forced(kz, monkeypatch):
+    """The direct organisation on an ordinary geometry (FDK_BP_DIRECT=1):
+    parity, binary16 storage, accumulation and z-slabs bitwise equal to the
+    full volume."""
+    monkeypatch.setenv("FDK_BP_DIRECT", "1")
+    if kz:
+        monkeypatch.setenv("FDK_BP_KZ", str(kz))
+    shape, (npv, nh, nw) = (37, 19, 33), (21, 45, 61)
+    scan = dict(wl.CONFIGS["c1"]["scan"], theta0=0.3, u_off=1.7, v_off=-2.2)
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    voxel, centre = (0.9, 1.1, 1.3), (2.0, -3.0, 1.5)
+    assert fdk.bp_plan(shape, voxel, npv, nh, nw, mats, centre)["lds_pitch"] == 0
+    proj = wl.gaussian(1400 + kz, (npv, nh, nw))
+    base = wl.gaussian(1450 + kz, shape)
+    got = gpu_bp(proj, mats, shape, voxel, centre, vol0=base)
+    ref = oracle.backproject(proj, mats, shape, voxel, centre, vol=base.astype(np.float64))
+    assert rel(got, ref) <= TOL32
+    full = gpu_bp(proj, mats, shape, voxel, centre)
+    p = torch.from_numpy(proj).cuda()
+    for k0, kc in [(0, 37), (3, 11), (36, 1)]:
+        slab = torch.zeros((kc,) + shape[1:], dtype=torch.float32, device="cuda")
+        fdk.backproject_slab(slab, shape, k0, p, mats, voxel, centre)
+        torch.cuda.synchronize()
+        assert np.array_equal(slab.cpu().numpy().view(np.uint32), full[k0:k0 + kc].view(np.uint32))
+    h, s = fdk.quantize_f16(p)
+    vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    fdk.backproject(vol, h, mats, voxel, centre, scale=s)
+    torch.cuda.synchronize()
+    ref16 = oracle.backproject(h.cpu().numpy(), mats, shape, voxel, centre, scale=s.cpu().numpy())
+    assert rel(vol.cpu().numpy(), ref16) <= TOL32

@@ -70,6 +70,10 @@ __device__ __forceinline__ float lerp_pair_f16(unsigned x, float fu)
     return h;
 }
 
+// Launch pitches from which the back-projector's per-(column, view) set-up
+// runs in FP64 (windows that wide arise only under strong magnification).
+constexpr int kPreciseSetupPitch = 120;
+
 struct BpArgs {
     const void* proj;
     const float* scale;
@@ -116,19 +120,28 @@ __device__ __forceinline__ void stage_rows(float* tile, int ralloc, const __amdg
         const int cs = F16 ? (c0 & ~1) : c0;                  // first staged pixel
         const int span = F16 ? 8 * SEG + 1 : 4 * SEG;         // pixels a row's loads read
         if (cs >= 0 && cs + span <= nw) {
+            // The descriptor's range check zeroes the rows outside the
+            // detector: a row above it has a negative offset (>= 2^31 as
+            // unsigned), a row below it an offset >= the view's bytes (< 2^31).
+            // The odd-offset pairs of binary16 rows are the same loads 2 bytes
+            // further (the instruction's immediate offset).
+            // A window wholly above or below the detector is zero wherever it
+            // starts: clamping its first row to [-R, nh] (descending: [-1,
+            // nh + R - 1]) keeps every offset within +-(nh + R) rows, which
+            // the launch plan bounds below 2^31 bytes.
+            const int r0c = REV ? min(max(r0, -1), nh + R - 1) : min(max(r0, -R), nh);
             const int rsub = lane / SEG, sg = lane - rsub * SEG;
-            const unsigned colb = (unsigned)cs * (F16 ? 2u : 4u) + 16u * (unsigned)sg;
-            for (int rr0 = wave * RPI; rr0 < R; rr0 += kWaves * RPI) {
-                const int rr = rr0 + rsub;
-                if (rsub < RPI && rr < R) {
-                    const int r = REV ? r0 - rr : r0 + rr;
-                    const unsigned vo = (unsigned)r < (unsigned)nh ? (unsigned)r * row_bytes + colb : kOut;
+            const int colb = cs * (F16 ? 2 : 4) + 16 * sg;
+            const int rstep = kWaves * RPI;
+            const int ostep = (REV ? -rstep : rstep) * (int)row_bytes;
+            int vo = (REV ? r0c - (wave * RPI + rsub) : r0c + wave * RPI + rsub) * (int)row_bytes + colb;
+            for (int rr0 = wave * RPI; rr0 < R; rr0 += rstep, vo += ostep) {
+                if (rsub < RPI && rr0 + rsub < R) {
                     lds_void* d = (lds_void*)(size_t)lds_addr(tile + rr0 * RW);
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, vo, 0, 0, 0);
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 16, (unsigned)vo, 0, 0, 0);
                     if (F16) {
                         lds_void* d2 = (lds_void*)(size_t)lds_addr(tile + (ralloc + rr0) * RW);
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d2, 16, vo == kOut ? kOut : vo + 2u,
-                                                                 0, 0, 0);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d2, 16, (unsigned)vo, 0, 2, 0);
                     }
                 }
             }
@@ -693,7 +706,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const int tid = threadIdx.x;
     const int wave = uniform(tid >> 6), lane = tid & 63;
     const int lx = tid & (kTile - 1), ly = tid >> 4;
-    const bool active = lx < ni && ly < nj;
     // idle lanes of an edge tile shadow a real column so that every LDS read
     // stays inside the staged footprint
     const float di = (float)min(lx, ni - 1), dj = (float)min(ly, nj - 1);
@@ -713,7 +725,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         if (tid < nb) {
             const int s = sb + tid;
             const float sc = A.scale ? A.scale[s] : 1.0f;
-            view_record(A.M + 12 * (size_t)s, i0, j0, ni, nj, kc, KZ, sc, PITCH, A.rows, true,
+            // opaque copies of the block's tile origin: the FP64 set-up derived
+            // from them is recomputed per batch rather than hoisted out of the
+            // view loop into registers that the accumulators need
+            int bi0 = i0, bj0 = j0, bkc = kc;
+            asm volatile("" : "+s"(bi0), "+s"(bj0), "+s"(bkc));
+            view_record(A.M + 12 * (size_t)s, bi0, bj0, ni, nj, bkc, KZ, sc, PITCH, A.rows, true,
                         &vtab[tid]);
         }
         __syncthreads();
@@ -727,29 +744,68 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                                    uniform(rv.R), C, wave, lane);
             __builtin_amdgcn_s_waitcnt(0);                    // this wave's LDS writes landed
             __syncthreads();
-            // ---- hoisted per (column, view) quantities
-            const float w = fmaf(uniform(rv.d), di, fmaf(uniform(rv.e), dj, uniform(rv.w0)));
-            float F = __builtin_amdgcn_rcpf(w);
-            F = F * fmaf(-w, F, 2.0f);                        // one Newton step
-            const float u = fmaf(uniform(rv.a), di, fmaf(uniform(rv.b), dj, uniform(rv.N0))) * F;
-            const float dv = uniform(rv.m12) * F;
-            const float W = F * F * uniform(rv.scale);
-            const float fu = __builtin_amdgcn_fractf(u);
-            // LDS byte address of the pair word of column floor(u) in tile row 0
-            // (u >= 1 inside the tile); binary16 tiles hold even- and odd-offset
-            // pairs in two regions
+            // ---- hoisted per (column, view) quantities: fu, the weight W,
+            // dv, the row origins of the two halves and the LDS address of
+            // column floor(u) in tile row 0 (u >= 1 inside the tile)
+            float fu, W, dv, v0h[2];
+            int iu;
+            if constexpr (PITCH >= kPreciseSetupPitch) {
+                // Strong magnification: window-relative coordinates reach
+                // ~PITCH columns and rows, where FP32 set-up error (~1 ulp of
+                // the coordinate) would move the taps by 1e-5 pixels; the
+                // set-up runs in FP64 from the view's matrix, and only u's
+                // fraction and the row origins are rounded to FP32.
+                const double* m = A.M + 12 * (size_t)(sb + qv);
+                const double i = (double)i0 + (double)di, j = (double)j0 + (double)dj;
+                const double Fd = 1.0 / (m[8] * i + m[9] * j + m[11]);
+                const double ud = (m[0] * i + m[1] * j + m[3]) * Fd - (double)c0;
+                const double fl = floor(ud);
+                fu = (float)(ud - fl);
+                iu = (int)fl;
+                dv = (float)(m[6] * Fd);
+                W = (float)(Fd * Fd) * rv.scale;
+                const double vij = m[4] * i + m[5] * j + m[7];
+                const int split = uniform(rv.split);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    // absolute first row of half q's window
+                    const int org = ((split && q) ? uniform(rv.r1) : uniform(rv.r0)) +
+                                    uniform(rv.half[q].row);
+                    v0h[q] = (float)((vij + m[6] * (double)(kc + q * (KZ / 2))) * Fd - (double)org);
+                }
+            } else {
+                // the record's float fields are used as broadcast LDS reads
+                // (moving each to a scalar register would cost one more VALU
+                // instruction per view)
+                const float w = fmaf(rv.d, di, fmaf(rv.e, dj, rv.w0));
+                float F = __builtin_amdgcn_rcpf(w);
+                F = F * fmaf(-w, F, 2.0f);                    // one Newton step
+                const float u = fmaf(rv.a, di, fmaf(rv.b, dj, rv.N0)) * F;
+                dv = rv.m12 * F;
+                W = F * F * rv.scale;
+                fu = __builtin_amdgcn_fractf(u);
+                iu = (int)u;
+                v0h[0] = v0h[1] = F;                          // origins: see v_origin
+            }
+            // binary16 tiles hold even- and odd-offset pairs in two regions
             unsigned base;
             if (F16) {
-                const int j = (int)u + (uniform(rv.c0) & 1);
-                base = tile_base + 4u * (unsigned)((j >> 1) + ((j & 1) ? A.rows * (PITCH / 2) : 0));
+                const int jc = iu + (c0 & 1);
+                base = tile_base + 4u * (unsigned)((jc >> 1) + ((jc & 1) ? A.rows * (PITCH / 2) : 0));
             } else {
-                base = tile_base + 4u * (unsigned)(int)u;
+                base = tile_base + 4u * (unsigned)iu;
             }
             // ---- hot loop: KZ updates of this column for this view, in two
             // halves; a footprint taller than the LDS tile is staged per half
             auto v_origin = [&](int q) {
-                const HalfBase& hb = rv.half[q];
-                return fmaf(uniform(hb.g), di, fmaf(uniform(hb.h), dj, uniform(hb.V0))) * F;
+                if constexpr (PITCH >= kPreciseSetupPitch) {
+                    return v0h[q];
+                } else {
+                    // computed where used (v0h holds 1 / w), which keeps the
+                    // second half's origin out of the registers of the first
+                    const HalfBase& hb = rv.half[q];
+                    return fmaf(hb.g, di, fmaf(hb.h, dj, hb.V0)) * v0h[0];
+                }
             };
             auto row_base = [&](int q) {
                 return base + (unsigned)(uniform(rv.half[q].row) * 4 * TileRow<PITCH, F16>::W);
@@ -776,9 +832,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         }
     }
 
-    // ---- one read-modify-write of the volume per call
-    if (active) {
-        const int i = i0 + lx, j = j0 + ly;
+    // ---- one read-modify-write of the volume per call (the column is
+    // re-derived from the thread index, so that it need not stay live
+    // through the view loop)
+    int tid_end = tid;
+    asm volatile("" : "+v"(tid_end));
+    if ((tid_end & (kTile - 1)) < ni && (tid_end >> 4) < nj) {
+        const int i = i0 + (tid_end & (kTile - 1)), j = j0 + (tid_end >> 4);
 #pragma unroll
         for (int kk = 0; kk < KZ; ++kk) {
             const int k = kc + kk;

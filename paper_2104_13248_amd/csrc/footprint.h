@@ -40,18 +40,18 @@ static_assert(sizeof(ViewRec) == 24 * 4, "view record is 24 words");
 __device__ inline void footprint_rows(const double* __restrict__ m, const double* ii,
                                       const double* jj, double ka, double kb, int* first, int* count)
 {
-    double vmin = 1e300, vmax = -1e300;
+    double vmin = 0.0, vmax = 0.0;       // seeded by the first corner
 #pragma unroll 1
-    for (int a = 0; a < 2; ++a)
-#pragma unroll 1
-        for (int b = 0; b < 2; ++b) {
-            const double rw = 1.0 / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
-            const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
-            const double v0 = (A + m[6] * ka) * rw;
-            const double v1 = (A + m[6] * kb) * rw;
-            vmin = fmin(vmin, fmin(v0, v1));
-            vmax = fmax(vmax, fmax(v0, v1));
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int a = q & 1, b = q >> 1;
+        const double rw = 1.0 / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
+        const double A = m[4] * ii[a] + m[5] * jj[b] + m[7];
+        const double v0 = (A + m[6] * ka) * rw;
+        const double v1 = (A + m[6] * kb) * rw;
+        const double lo = fmin(v0, v1), hi = fmax(v0, v1);
+        vmin = q ? fmin(vmin, lo) : lo;
+        vmax = q ? fmax(vmax, hi) : hi;
+    }
     const double f0 = floor(vmin), f1 = floor(vmax);
     *first = (int)f0 - 1;
     *count = (int)(f1 - f0) + 4;
@@ -68,15 +68,14 @@ __device__ inline void view_record(const double* __restrict__ m, int i0, int j0,
 {
     const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
     const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
-    double umin = 1e300, umax = -1e300;
+    double umin = 0.0, umax = 0.0;       // seeded by the first corner
 #pragma unroll 1
-    for (int a = 0; a < 2; ++a)
-#pragma unroll 1
-        for (int b = 0; b < 2; ++b) {
-            const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int a = q & 1, b = q >> 1;
+        const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
+        umin = q ? fmin(umin, u) : u;
+        umax = q ? fmax(umax, u) : u;
+    }
     const double fu0 = floor(umin), fu1 = floor(umax);
     const int c0 = (int)fu0 - 1;
     int C = (int)(fu1 - fu0) + 4;
@@ -141,15 +140,14 @@ __device__ inline void view_record_sym(const double* __restrict__ m, int i0, int
 {
     const double ii[2] = {(double)i0, (double)(i0 + ni - 1)};
     const double jj[2] = {(double)j0, (double)(j0 + nj - 1)};
-    double umin = 1e300, umax = -1e300;
+    double umin = 0.0, umax = 0.0;       // seeded by the first corner
 #pragma unroll 1
-    for (int a = 0; a < 2; ++a)
-#pragma unroll 1
-        for (int b = 0; b < 2; ++b) {
-            const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
-            umin = fmin(umin, u);
-            umax = fmax(umax, u);
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int a = q & 1, b = q >> 1;
+        const double u = (m[0] * ii[a] + m[1] * jj[b] + m[3]) / (m[8] * ii[a] + m[9] * jj[b] + m[11]);
+        umin = q ? fmin(umin, u) : u;
+        umax = q ? fmax(umax, u) : u;
+    }
     const double fu0 = floor(umin), fu1 = floor(umax);
     const int c0 = (int)fu0 - 1;
     int C = (int)(fu1 - fu0) + 4;

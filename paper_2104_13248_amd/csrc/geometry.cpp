@@ -215,6 +215,16 @@ uint64_t fnv1a(uint64_t h, const void* p, size_t n)
 std::mutex g_plan_mu;
 std::list<std::pair<uint64_t, BpPlan>> g_plans;   // most recent first
 
+// The kernels stage a window of R rows by buffer loads whose byte offsets,
+// with the window's first row clamped to [-R, nh] (rows wholly outside the
+// detector read as zero either way), lie within +-(nh + R) rows of the view;
+// they must stay below 2^31.
+bool staging_offsets_fit(const fdk_stack& sg, int rows)
+{
+    const int64_t rb = (int64_t)sg.nw * (sg.dtype == FDK_F16 ? 2 : 4);
+    return ((int64_t)sg.nh + rows + 1) * rb < (1ll << 31);
+}
+
 int env_int(const char* name, int dflt)
 {
     const char* s = std::getenv(name);
@@ -306,6 +316,11 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
             best.rows = r;
             best.lds_bytes = (int64_t)best.rows * best.pitch * 4 + table_bytes;
         }
+        if (!staging_offsets_fit(sg, best.rows)) {
+            best = BpPlan();
+            best.kz = kz_force ? kz_force : 32;
+            best.direct = true;
+        }
     }
     best.ntx = (vg.nx + kTile - 1) / kTile;
     best.nty = (vg.ny + kTile - 1) / kTile;
@@ -327,7 +342,6 @@ fdk_status make_bp_plan(const fdk_volume& vg, const fdk_stack& sg,
 fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
                             const std::vector<IndexMatrix>& M, BpPlan& plan)
 {
-    (void)sg;
     const int kz_force = env_int("FDK_BP_KZ", 0);
     const int lds_budget = env_int("FDK_BP_SYM_LDS_BUDGET", 38 * 1024);
     const int cands[3] = {32, 16, 8};
@@ -363,6 +377,8 @@ fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
         return fail(FDK_E_UNSUPPORTED,
                     "projection footprint of a 16x16x8 voxel block does not fit in LDS "
                     "(magnification too large for the detector pitch)");
+    if (!staging_offsets_fit(sg, best.rows))
+        return fail(FDK_E_UNSUPPORTED, "views too large for the symmetric variant's staging offsets");
     best.ntx = (vg.nx + kTile - 1) / kTile;
     best.nty = (vg.ny + kTile - 1) / kTile;
     best.ntiles_pad = ((best.ntx * best.nty + 7) / 8) * 8;
@@ -382,7 +398,6 @@ fdk_status make_bp_plan_sym(const fdk_volume& vg, const fdk_stack& sg,
 fdk_status make_bp_plan_subline(const fdk_volume& vg, const fdk_stack& sg,
                                 const std::vector<IndexMatrix>& M, BpPlan& plan)
 {
-    (void)sg;
     const int kz_force = env_int("FDK_BP_KZ", 0);
     const int lds_budget = env_int("FDK_BP_SUBLINE_LDS_BUDGET", 76 * 1024);
     double dv_max = 0.0;
@@ -408,6 +423,8 @@ fdk_status make_bp_plan_subline(const fdk_volume& vg, const fdk_stack& sg,
         const int64_t bytes = (int64_t)e.rows_full * pitch * 4 + (int64_t)line_rows * kThreads * 4 +
                               table_bytes;
         if (bytes > lds_budget && !(kz_force && bytes <= 150 * 1024)) continue;
+        if (!staging_offsets_fit(sg, e.rows_full))
+            return fail(FDK_E_UNSUPPORTED, "views too large for the sub-line variant's staging offsets");
         plan.kz = kz;
         plan.pitch = pitch;
         plan.rows = e.rows_full;

@@ -152,6 +152,42 @@ def test_c1_f16_storage():
     assert e16 <= TOL32
 
 
+OFF_DETECTOR = [
+    # shape (nz, ny, nx), (np, nh, nw), centre: windows of blocks far above,
+    # far below and partly beside the detector rows (a window's first row
+    # many window heights outside the detector, where the staging clamps it)
+    ((40, 24, 24), (16, 20, 64), (0.0, 0.0, 260.0)),
+    ((40, 24, 24), (16, 20, 64), (0.0, 0.0, -260.0)),
+    ((70, 24, 24), (16, 20, 64), (0.0, 0.0, 30.0)),
+]
+
+
+@pytest.mark.parametrize("f16", [False, True])
+@pytest.mark.parametrize("case", range(len(OFF_DETECTOR)))
+def test_windows_off_detector(case, f16):
+    shape, (npv, nh, nw), centre = OFF_DETECTOR[case]
+    scan = wl.CONFIGS["c1"]["scan"]
+    mats = og.scan_matrices(scan, npv, nh, nw)
+    proj = wl.gaussian(400 + case, (npv, nh, nw))
+    voxel = (1.0, 1.0, 1.0)
+    log("off detector", case, shape, centre, "f16" if f16 else "f32")
+    if f16:
+        h, sc = fdk.quantize_f16(torch.from_numpy(proj).cuda())
+        vol = torch.zeros(shape, dtype=torch.float32, device="cuda")
+        fdk.backproject(vol, h, mats, voxel, centre, scale=sc)
+        torch.cuda.synchronize()
+        got = vol.cpu().numpy()
+        ref = oracle.backproject(h.cpu().numpy(), mats, shape, voxel, centre, scale=sc.cpu().numpy())
+    else:
+        got = gpu_bp(proj, mats, shape, voxel, centre)
+        ref = oracle.backproject(proj, mats, shape, voxel, centre)
+    e = rel(got, ref)
+    log("rel-L2", e, "nonzero", int(np.count_nonzero(ref)))
+    assert e <= TOL32
+    if not np.any(ref):
+        assert not np.any(got)
+
+
 def _sample_voxels(shape, n, seed):
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)

@@ -91,7 +91,9 @@ __global__ __launch_bounds__(kThreads) void fp_kernel(const FpArgs A)
         // interval of a per volume row b, bounded by the solutions of u(a) = c -/+ 1
         const double tl = (double)c - 1.0, th = (double)c + 1.0;
         const double dl = ua - tl * wa, dh = ua - th * wa;
-        const bool solvable = dl != 0.0 && dh != 0.0;
+        // both ends on one branch of the Moebius function (its asymptote u = ua / wa
+        // outside [tl, th]); otherwise the interval is the whole row
+        const bool solvable = dl != 0.0 && dh != 0.0 && (dl > 0.0) == (dh > 0.0);
         const double il = solvable ? 1.0 / dl : 0.0, ih = solvable ? 1.0 / dh : 0.0;
         for (int b = 0; b < nb; ++b) {
             const double db = (double)b;
@@ -251,7 +253,9 @@ __global__ __launch_bounds__(64) void fp_voxel_kernel(const FpArgs A)
     // left taps in window columns 0 .. cw: u in [c0 - 1, c0 + cw)
     const double tl = (double)c0 - 1.0, th = (double)(c0 + cw);
     const double dl = ua - tl * wa, dh = ua - th * wa;
-    const bool solvable = dl != 0.0 && dh != 0.0;
+    // both ends on one branch of the Moebius function (its asymptote u = ua / wa
+    // outside [tl, th]); otherwise the interval is the whole row
+    const bool solvable = dl != 0.0 && dh != 0.0 && (dl > 0.0) == (dh > 0.0);
     const double il = solvable ? 1.0 / dl : 0.0, ih = solvable ? 1.0 / dh : 0.0;
 
     for (int b = 0; b < nb; ++b) {

@@ -380,3 +380,22 @@ def test_plan_tile_grows_to_four_blocks_per_cu(name, monkeypatch):
     if p16["lds_rows"] > base["lds_rows"]:
         assert p16["lds_rows"] % 8 == 4 and p16["lds_rows"] <= fit
         assert (p16["lds_rows"] * base["lds_pitch"] // 2) % 32 == 16
+
+
+def test_plan_takes_direct_taps_when_staging_offsets_could_overflow():
+    """The staging loop addresses a window's rows by one signed 32-bit byte
+    offset per lane, its first row clamped to [-R, nh]: the plan keeps the LDS
+    tile only while (nh + rows + 1) rows of a view stay below 2^31 bytes, and
+    otherwise takes the direct organisation (lds_pitch = 0).  Host only."""
+    scan = dict(wl.CONFIGS["c1"]["scan"])
+    shape, voxel = (32, 32, 32), (1.0, 1.0, 1.0)
+    nh = 1024
+    ok = 8192                                    # 32 MiB views
+    edge = (2 ** 31 - 1) // (4 * nh)             # a float32 view just under 2 GiB
+    for nw, direct in ((ok, False), (edge, True)):
+        mats = og.scan_matrices(scan, 2, nh, nw)
+        plan = fdk.bp_plan(shape, voxel, 2, nh, nw, mats)
+        assert (plan["lds_pitch"] == 0) == direct, (nw, plan)
+        # binary16 views of the same width are half as large: the tile stays
+        plan16 = fdk.bp_plan(shape, voxel, 2, nh, nw, mats, f16=True)
+        assert plan16["lds_pitch"] > 0, (nw, plan16)

@@ -259,8 +259,14 @@ __device__ __forceinline__ float bilinear(const unsigned (&t)[4], float fu, floa
 {
     float h0, h1;
     if (F16) {
-        h0 = lerp_pair_f16(t[0], fu);
-        h1 = lerp_pair_f16(t[2], fu);
+        // lerp_pair_f16 of both rows, the two rows' differences first: no
+        // instruction then reads the result of the one just before it (a
+        // hazard wait after each mixed-precision FMA otherwise)
+        float d0, d1;
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(d0) : "v"(t[0]));
+        asm("v_fma_mix_f32 %0, %1, 1.0, -%1 op_sel:[1,0,0] op_sel_hi:[1,0,1]" : "=v"(d1) : "v"(t[2]));
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(h0) : "v"(fu), "v"(d0), "v"(t[0]));
+        asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[0,0,1]" : "=v"(h1) : "v"(fu), "v"(d1), "v"(t[2]));
     } else {
         const float p00 = __builtin_bit_cast(float, t[0]), p01 = __builtin_bit_cast(float, t[1]);
         const float p10 = __builtin_bit_cast(float, t[2]), p11 = __builtin_bit_cast(float, t[3]);

@@ -5,7 +5,8 @@
 // with (u w, v w, w) = M_s (i, j, k, 1) and zero outside the detector.
 //
 // How (GPU design; the paper's CPU kernels are prior art):
-//   * one thread per voxel column (i, j) of a 16 x 16 tile; each thread keeps
+//   * one thread per voxel column (i, j) of a 16 x 16 tile, each wave an 8 x 8
+//     quarter of it; each thread keeps
 //     KZ consecutive slices of its column in registers for the WHOLE view
 //     loop, so the volume is read and written once per call (the paper's
 //     batching with register accumulation, Section 3.1.3, taken to nb = np);
@@ -16,19 +17,21 @@
 //     LDS with zero padding (the local-memory staging of Section 3.2, without
 //     a per-update bounds check).  Each wave stages whole detector rows:
 //     float32 rows go straight from memory into LDS (buffer loads with the
-//     LDS-direct bit, no VGPR round trip); out-of-range buffer offsets make
-//     columns outside the detector read as zero, rows outside it are zeroed;
+//     LDS-direct bit, no VGPR round trip); the buffer's range check makes
+//     rows and columns outside the detector read as zero;
 //   * the LDS tile is sized for nearly every (block, view) footprint; the
 //     rare taller ones (blocks near the source at a large cone angle) are
 //     staged and consumed in two half-chunks of slices, which keeps the LDS
 //     per block small and the occupancy high;
-//   * binary16 stacks are staged as (p[c], p[c+1]) pairs in one LDS word (the
-//     right neighbour arrives by a DPP lane shift), so one LDS read yields
-//     both horizontal taps and the lerps run as mixed-precision FMAs on the
-//     binary16 halves: FP32 arithmetic, half the LDS bytes per update;
-//   * FP64 is used only to compose the index-space matrices and the per-block,
-//     per-view bases (coordinates relative to the staged tile), which keeps
-//     the FP32 coordinates small and accurate;
+//   * binary16 stacks are staged as (p[c], p[c+1]) pairs in one LDS word, in
+//     two regions (pairs at even and at odd offsets, the second loaded 2
+//     bytes further), so one LDS read yields both horizontal taps and the
+//     lerps run as mixed-precision FMAs on the binary16 halves: FP32
+//     arithmetic, half the LDS bytes per update;
+//   * FP64 composes the index-space matrices and the per-block, per-view
+//     bases (coordinates relative to the staged tile, which keeps the FP32
+//     coordinates small and accurate); launches with windows 120 words wide
+//     or more also run each thread's per-view set-up in FP64;
 //   * block order: z-chunk major so that the resident blocks cover a thin
 //     slab and read a narrow band of detector rows; within a chunk each of
 //     the 8 XCDs receives a contiguous band of tiles (blocks are dealt to

@@ -280,7 +280,8 @@ __device__ __forceinline__ float bilinear(const unsigned (&t)[4], float fu, floa
 }
 
 // KZ/2 consecutive updates kk = k0 + t, t = 0 .. KZ/2 - 1, of one column for
-// one view; v = v0 + t dv is the row coordinate relative to the half's origin,
+// one view; v = v0 + t dv (v0 itself at t = 0: the compiler cannot drop an FMA
+// by zero) is the row coordinate relative to the half's origin,
 // whose LDS row address (plus the column) is `base`.  Tap loads run
 // kPrefetch updates ahead of their use.
 template <int KZ, int PITCH, bool F16>
@@ -294,7 +295,7 @@ __device__ __forceinline__ void update_half(float (&acc)[KZ], int k0, unsigned b
         unsigned t[kPrefetch][4];
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q)
-            load_taps<PITCH, F16>(base, fmaf((float)(g0 + q), dv, v0), t[q], fv[q]);
+            load_taps<PITCH, F16>(base, g0 + q == 0 ? v0 : fmaf((float)(g0 + q), dv, v0), t[q], fv[q]);
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q)
             acc[k0 + g0 + q] = fmaf(W, bilinear<F16>(t[q], fu, fv[q]), acc[k0 + g0 + q]);
@@ -328,7 +329,8 @@ __device__ __forceinline__ void update_column(float (&acc)[KZ], unsigned base0, 
         const int t0 = k < H ? k : k - H;
 #pragma unroll
         for (int q = 0; q < G; ++q)
-            load_taps<PITCH, F16>(b, fmaf((float)(t0 + q), dv, v0), t[g & 1][q], fv[g & 1][q]);
+            load_taps<PITCH, F16>(b, t0 + q == 0 ? v0 : fmaf((float)(t0 + q), dv, v0), t[g & 1][q],
+                                  fv[g & 1][q]);
     };
     load_group(0);
 #pragma unroll

@@ -16,7 +16,9 @@
 // from one forward transform, a multiplication by H and one inverse transform.
 // A block owns such a pair of rows; the transforms are Stockham radix-16/8/4/2
 // passes in LDS (natural order in and out), the inverse taken as
-// conj(FFT(conj(.))) with 1/M and the FDK constants folded into H.  H and the
+// conj(FFT(conj(.))) with 1/M and the FDK constants folded into H, its radices
+// in the reverse order so that the forward's last pass, the product with H and
+// the inverse's first pass run in registers as one step.  H and the
 // twiddle factors are built per call in FP64.  Longer rows use a direct
 // convolution: one block per row, the weighted row and the odd-tap
 // coefficients in LDS, each q read once per pair of symmetric taps.
@@ -109,10 +111,21 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 }
 
 // In-place forward DFT of R = 2, 4, 8 or 16 points (kernel e^{-2 pi i n k / R}).
-template <int R>
+// HALF: v[R/2 ..] are zero on entry (the zero-padded half of a row), so the
+// first radix-2 stage of the even/odd split reduces to copies.
+template <int R, bool HALF = false>
 __device__ __forceinline__ void dft(float2 (&v)[R])
 {
-    if constexpr (R == 2) {
+    if constexpr (HALF && R == 2) {
+        v[1] = v[0];
+    } else if constexpr (HALF && R == 4) {
+        // (a, b, 0, 0) -> (a + b, a - i b, a - b, a + i b)
+        const float2 a = v[0], b = v[1];
+        v[0] = make_float2(a.x + b.x, a.y + b.y);
+        v[2] = make_float2(a.x - b.x, a.y - b.y);
+        v[1] = make_float2(a.x + b.y, a.y - b.x);
+        v[3] = make_float2(a.x - b.y, a.y + b.x);
+    } else if constexpr (R == 2) {
         const float2 a = v[0], b = v[1];
         v[0] = make_float2(a.x + b.x, a.y + b.y);
         v[1] = make_float2(a.x - b.x, a.y - b.y);
@@ -133,8 +146,8 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
             e[r] = v[2 * r];
             o[r] = v[2 * r + 1];
         }
-        dft<8>(e);
-        dft<8>(o);
+        dft<8, HALF>(e);
+        dft<8, HALF>(o);
         constexpr float c1 = 0.92387953251128676f, s1 = 0.38268343236508977f;
         constexpr float h = 0.70710678118654752f;
         const float2 w16[8] = {make_float2(1.f, 0.f), make_float2(c1, -s1), make_float2(h, -h),
@@ -151,8 +164,8 @@ __device__ __forceinline__ void dft(float2 (&v)[R])
         // X[k] = E[k] + W8^k O[k], X[k + 4] = E[k] - W8^k O[k]
         float2 e[4] = {v[0], v[2], v[4], v[6]};
         float2 o[4] = {v[1], v[3], v[5], v[7]};
-        dft<4>(e);
-        dft<4>(o);
+        dft<4, HALF>(e);
+        dft<4, HALF>(o);
         constexpr float h = 0.70710678118654752f;
         o[1] = make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));     // * (h, -h)
         o[2] = make_float2(o[2].y, -o[2].x);                                   // * -i
@@ -194,20 +207,37 @@ __device__ __forceinline__ void twiddles(float2 W, float2 (&w)[R])
     }
 }
 
+// Radix of the pass after sub-transforms of length NS: 16 while at least 16
+// remain, then the rest.
+__host__ __device__ constexpr int fft_radix(int M, int NS) { return M / NS >= 16 ? 16 : M / NS; }
+
+// Sub-transform length before the forward transform's last pass.
+__host__ __device__ constexpr int last_pass_ns(int M)
+{
+    int ns = 1;
+    while (ns * 16 < M) ns *= 16;
+    return ns;
+}
+
 // Stockham passes of a length-M forward DFT (natural order in and out), from
 // sub-transform length NS on.  Pass of radix R after sub-transforms of length
 // NS: butterfly j reads elements j + r M/R, twiddles them by
 // W_{NS R}^{(j mod NS) r}, and writes (j / NS) NS R + (j mod NS) + r NS.  The
 // first pass reads through first(e) and the last writes through last(e, v)
 // (FIRST_LDS / LAST_LDS: whether those touch the LDS buffer, which decides the
-// barriers); the passes in between use the buffer.
-template <int M, int T, int NS, bool FIRST_LDS, bool LAST_LDS, class First, class Last>
+// barriers); the passes in between use the buffer.  The passes stop at
+// sub-transform length NS_END.
+// HALF_IN: the input's upper half is zero (the first pass reads none of it);
+// HALF_OUT: only the output's lower half is used (the last pass neither
+// computes nor stores the rest).
+template <int M, int T, int NS, int NS_END, bool FIRST_LDS, bool LAST_LDS, bool HALF_IN,
+          bool HALF_OUT, class First, class Last>
 __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict__ tw, int tid,
                                            First first, Last last)
 {
-    if constexpr (NS < M) {
-        constexpr int R = M / NS >= 16 ? 16 : M / NS;
-        constexpr bool is_first = NS == 1, is_last = NS * R == M;
+    if constexpr (NS < NS_END) {
+        constexpr int R = fft_radix(M, NS);
+        constexpr bool is_first = NS == 1, is_last = NS * R == NS_END;
         constexpr bool load_lds = !is_first || FIRST_LDS;
         constexpr bool store_lds = !is_last || LAST_LDS;
         constexpr int B = M / R;
@@ -219,8 +249,11 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
             if (j < B) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if constexpr (is_first) v[q][r] = first(j + r * B);
-                    else v[q][r] = buf[fpad(j + r * B)];
+                    if constexpr (is_first) {
+                        v[q][r] = !HALF_IN || 2 * r < R ? first(j + r * B) : make_float2(0.f, 0.f);
+                    } else {
+                        v[q][r] = buf[fpad(j + r * B)];
+                    }
                 }
                 if constexpr (NS > 1) {
                     float2 w[R];
@@ -228,7 +261,7 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
                 }
-                dft<R>(v[q]);
+                dft<R, is_first && HALF_IN>(v[q]);
             }
         }
         if constexpr (load_lds && store_lds) __syncthreads();   // in place: all reads first
@@ -239,21 +272,76 @@ __device__ __forceinline__ void fft_passes(float2* buf, const float2* __restrict
                 const int d = (j / NS) * NS * R + j % NS;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if constexpr (is_last) last(d + r * NS, v[q][r]);
-                    else buf[fpad(d + r * NS)] = v[q][r];
+                    if constexpr (is_last) {
+                        if (!HALF_OUT || 2 * r < R) last(d + r * NS, v[q][r]);
+                    } else {
+                        buf[fpad(d + r * NS)] = v[q][r];
+                    }
                 }
             }
         }
         if constexpr (store_lds) __syncthreads();
-        fft_passes<M, T, NS * R, FIRST_LDS, LAST_LDS>(buf, tw, tid, first, last);
+        fft_passes<M, T, NS * R, NS_END, FIRST_LDS, LAST_LDS, HALF_IN, HALF_OUT>(buf, tw, tid,
+                                                                                first, last);
     }
+}
+
+// The forward transform's last pass and the inverse's first, fused in
+// registers: with the inverse's radices taken in the reverse order, both
+// passes read elements j + r NS_LAST for butterfly j (R = M / NS_LAST), so
+// each thread twiddles and transforms its elements, multiplies them by H
+// (real) and conjugates them (the inverse as conj(FFT(conj(.)))), transforms
+// them again as the inverse's first pass (no twiddles after sub-transforms of
+// length 1) and stores them to where that pass writes, element j R + r.
+template <int M, int T>
+__device__ __forceinline__ void fft_middle(float2* buf, const float2* __restrict__ tw,
+                                           const float* __restrict__ H, int tid)
+{
+    constexpr int NS = last_pass_ns(M);
+    constexpr int R = M / NS;
+    constexpr int B = NS;                          // butterflies of either pass
+    constexpr int J = (B + T - 1) / T;
+    float2 v[J][R];
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = tid + T * q;
+        if (j < B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[fpad(j + r * B)];
+            if constexpr (NS > 1) {
+                float2 w[R];
+                twiddles<R>(tw[j], w);
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+            }
+            dft<R>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const float h = H[j + r * NS];
+                v[q][r] = make_float2(v[q][r].x * h, -v[q][r].y * h);
+            }
+            dft<R>(v[q]);
+        }
+    }
+    __syncthreads();                               // in place: all reads first
+#pragma unroll
+    for (int q = 0; q < J; ++q) {
+        const int j = tid + T * q;
+        if (j < B) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[fpad(j * R + r)] = v[q][r];
+        }
+    }
+    __syncthreads();
 }
 
 // Threads of the Fourier-domain filter's block: one per radix-16 butterfly.
 template <int M>
 constexpr int fft_threads() { return M / 16 < 64 ? 64 : (M / 16 > 256 ? 256 : M / 16); }
 
-template <int M>
+// MAXB: also post the |output| maxima of each view to A.maxbits.  H holds
+// the factor sdd of the cosine weight besides 1/M and the FDK constants.
+template <int M, bool MAXB>
 __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const FilterArgs A,
                                                                     const float* __restrict__ H,
                                                                     const float2* __restrict__ tw,
@@ -265,8 +353,11 @@ __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const Filt
     const bool two = row0 + 1 < nrows;
     const float* s0 = A.raw + row0 * A.nw;
     const float* s1 = s0 + A.nw;
-    const float v0 = ((float)(int)(row0 % A.nh) - A.cv) * A.dv;
-    const float v1 = ((float)(int)((row0 + 1) % A.nh) - A.cv) * A.dv;
+    const int64_t view0 = row0 / A.nh;             // view and detector row of row0
+    const int r0 = (int)(row0 - view0 * A.nh);
+    const bool wrap = r0 + 1 == A.nh;              // row0 + 1 starts the next view
+    const float v0 = ((float)r0 - A.cv) * A.dv;
+    const float v1 = ((float)(wrap ? 0 : r0 + 1) - A.cv) * A.dv;
     const float w0 = A.sdd2 + v0 * v0, w1 = A.sdd2 + v1 * v1;
     // forward transform of z = a + i b, the two cosine-weighted rows (zero
     // beyond nw), read straight from the stack by the first pass
@@ -274,17 +365,16 @@ __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const Filt
         float a = 0.f, b = 0.f;
         if (c < A.nw) {
             const float umm = ((float)c - A.cu) * A.du;
-            a = s0[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w0)));
-            if (two) b = s1[c] * (A.sdd * rsqrtf(fmaf(umm, umm, w1)));
+            a = s0[c] * rsqrtf(fmaf(umm, umm, w0));
+            if (two) b = s1[c] * rsqrtf(fmaf(umm, umm, w1));
         }
         return make_float2(a, b);
     };
     auto to_buf = [&](int e, float2 v) { buf[fpad(e)] = v; };
     constexpr int T = fft_threads<M>();
-    fft_passes<M, T, 1, false, true>(buf, tw, tid, weighted, to_buf);
-    // inverse transform as conj(FFT(conj(Z H))) (H is real and holds 1/M):
-    // the first pass reads conj(Z H), the last writes row a = Re, row b = -Im
-    // of the first nw outputs straight to the stack
+    // inverse transform as conj(FFT(conj(Z H))) (H is real and holds 1/M);
+    // its last pass writes row a = Re, row b = -Im of the first nw outputs
+    // straight to the stack
     auto conj_zh = [&](int k) {
         const float2 z = buf[fpad(k)];
         const float h = H[k];
@@ -295,22 +385,34 @@ __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const Filt
     auto to_rows = [&](int c, float2 y) {
         if (c < A.nw) {
             d0[c] = y.x;
-            m0 = fmaxf(m0, fabsf(y.x));
+            if constexpr (MAXB) m0 = fmaxf(m0, fabsf(y.x));
             if (two) {
                 d0[A.nw + c] = -y.y;
-                m1 = fmaxf(m1, fabsf(y.y));
+                if constexpr (MAXB) m1 = fmaxf(m1, fabsf(y.y));
             }
         }
     };
-    fft_passes<M, T, 1, true, false>(buf, tw, tid, conj_zh, to_rows);
-    if (A.maxbits) {
+    // M >= 2 nw (M is even and at least 2 nw - 1): the forward input's upper
+    // half is padding and the inverse output's upper half is not stored
+    constexpr int NSL = last_pass_ns(M);
+    if constexpr (NSL > 1) {
+        // forward passes up to the last, the fused middle, then the inverse
+        // passes after its first (radix M / NSL)
+        fft_passes<M, T, 1, NSL, false, true, true, false>(buf, tw, tid, weighted, to_buf);
+        fft_middle<M, T>(buf, tw, H, tid);
+        fft_passes<M, T, M / NSL, M, true, false, false, true>(buf, tw, tid, conj_zh, to_rows);
+    } else {
+        // one pass each way
+        fft_passes<M, T, 1, M, false, true, true, false>(buf, tw, tid, weighted, to_buf);
+        fft_passes<M, T, 1, M, true, false, false, true>(buf, tw, tid, conj_zh, to_rows);
+    }
+    if constexpr (MAXB) {
         __shared__ float part[2][4];
-        const int64_t s0v = row0 / A.nh, s1v = (row0 + 1) / A.nh;
-        if (!two || s0v == s1v) {
-            post_block_max(fmaxf(m0, m1), part[0], A.maxbits, s0v);
+        if (!two || !wrap) {
+            post_block_max(fmaxf(m0, m1), part[0], A.maxbits, view0);
         } else {
-            post_block_max(m0, part[0], A.maxbits, s0v);
-            post_block_max(m1, part[1], A.maxbits, s1v);
+            post_block_max(m0, part[0], A.maxbits, view0);
+            post_block_max(m1, part[1], A.maxbits, view0 + 1);
         }
     }
 }
@@ -391,7 +493,7 @@ namespace {
 
 // Filter the rows of A (A.raw, A.out already offset to the first view):
 // nviews views of a.nh rows.  tw/H: the Fourier tables (nullptr for rows
-// longer than kFftMaxRow).
+// longer than kFftMaxRow); A.maxbits selects the kernels that post maxima.
 fdk_status filter_rows(const FilterArgs& A, int32_t nviews, int32_t nh, int32_t nw, int M,
                        const float* H, const float2* tw, hipStream_t st)
 {
@@ -399,7 +501,15 @@ fdk_status filter_rows(const FilterArgs& A, int32_t nviews, int32_t nh, int32_t 
     if (nw <= kFftMaxRow) {
         const dim3 g((unsigned)((rows + 1) / 2));
         switch (M) {
-#define FDK_FFT(m) case m: hipLaunchKernelGGL(filter_fft_kernel<m>, g, dim3(fft_threads<m>()), 0, st, A, H, tw, rows); break;
+#define FDK_FFT(m)                                                                       \
+    case m:                                                                              \
+        if (A.maxbits)                                                                   \
+            hipLaunchKernelGGL((filter_fft_kernel<m, true>), g, dim3(fft_threads<m>()), 0, \
+                               st, A, H, tw, rows);                                      \
+        else                                                                             \
+            hipLaunchKernelGGL((filter_fft_kernel<m, false>), g, dim3(fft_threads<m>()), 0, \
+                               st, A, H, tw, rows);                                      \
+        break;
             FDK_FFT(16) FDK_FFT(32) FDK_FFT(64) FDK_FFT(128) FDK_FFT(256) FDK_FFT(512)
             FDK_FFT(1024) FDK_FFT(2048) FDK_FFT(4096)
 #undef FDK_FFT
@@ -444,12 +554,13 @@ fdk_status launch_filter(const FilterLaunch& a, void* stream)
         if (s != FDK_OK) return s;
         tw = (float2*)tab;
         H = (float*)(tw + M);
+        // H carries the factor sdd of the cosine weight
         const double tau = a.du * a.sod / a.sdd;
         const double wang = a.arc / (2.0 * (double)a.np_total);
         const double pi = 3.14159265358979323846;
         hipLaunchKernelGGL(filter_tables_kernel, dim3(M), dim3(64), 0, st, M, a.nw,
-                           1.0 / (4.0 * tau * tau) * tau * wang, -1.0 / (pi * pi * tau * tau) * tau * wang,
-                           tw, H);
+                           1.0 / (4.0 * tau * tau) * tau * wang * a.sdd,
+                           -1.0 / (pi * pi * tau * tau) * tau * wang * a.sdd, tw, H);
         s = check_launch("filter table kernel");
     }
     if (s == FDK_OK && !a.out16) {

@@ -212,6 +212,30 @@ def test_filter_ragged_rows(nw):
     assert rel(out.cpu().numpy(), ref) <= TOL32
 
 
+# Both ends of every transform length's row range (M = the power of two
+# >= 2 nw - 1, at least 16): nw = M / 2 fills the unpadded half exactly,
+# nw = M / 4 + 1 is the narrowest row of that length.
+@pytest.mark.parametrize("nw", [8, 9, 16, 17, 32, 33, 64, 65, 128, 129, 256, 257, 512, 513,
+                                1024, 1025])
+def test_filter_every_transform_length(nw):
+    """Float32 output against the FP64 filter, and the binary16 output (the
+    kernels that also take the per-view maxima) bit for bit against the
+    storage rule applied to that float32 output.  Five rows per view: row
+    pairs that span two views."""
+    scan = dict(sod=600.0, sdd=1100.0, du=0.8, dv=1.2, arc=2 * math.pi, theta0=0.0,
+                u_off=-2.5, v_off=0.5)
+    raw = wl.gaussian(800 + nw, (3, 5, nw))
+    raw_d = torch.from_numpy(raw).cuda()
+    out = fdk.fdk_filter(raw_d, scan, np_total=360)
+    h, s = fdk.fdk_filter(raw_d, scan, np_total=360, dtype=torch.float16)
+    torch.cuda.synchronize()
+    ref = oracle.fdk_filter(raw.astype(np.float64), scan, np_total=360)
+    assert rel(out.cpu().numpy(), ref) <= TOL32
+    h_ref, s_ref = oracle.quantize_f16(out.cpu().numpy())
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), s_ref.view(np.uint32))
+    assert np.array_equal(h.cpu().numpy().view(np.uint16), h_ref.view(np.uint16))
+
+
 F16_FILTER_CASES = [
     # (np, nh, nw), raw: "phantom" (C1 phantom views) or "gaussian"
     ((64, 128, 128), "phantom"),

@@ -56,8 +56,9 @@ LDS_NOMINAL_GBS = 256 * 128 * 2.4e9 / 1e9
 TAP_BYTES = {"f16": 8, "f32": 16}
 # Measured HBM traffic of the back-projection kernel (FETCH_SIZE + WRITE_SIZE,
 # scaled by a plain copy of known size) and the hash of the sources it was
-# taken on, per storage.
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "bp_kernel_c3_1024cube_2048views_traffic.md")
+# taken on, per storage; one summary per workload.
+TRAFFIC_PROFILES = tuple(os.path.join(ROOT, "profiles", f) for f in (
+    "bp_kernel_c3_1024cube_2048views_traffic.md", "bp_kernel_c2_512cube_1024views_traffic.md"))
 KERNEL_SOURCES = ("bp.hip", "footprint.h", "internal.h", "geometry.cpp")
 TOL = {"f32": 1e-5, "f16": 1e-3}
 
@@ -72,21 +73,23 @@ def kernel_source_hash() -> str:
 
 def measured_traffic(workload: str, storage: str):
     """HBM bytes per launch of the back-projection for one storage from the
-    committed counter summary, or None if it is missing, for another
-    workload, or taken on other kernel sources."""
-    try:
-        text = open(TRAFFIC_PROFILE).read()
-    except OSError:
-        return None
-    fields = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", text, flags=re.M))
-    if fields.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    if fields.get("workload") != workload:
-        return None
-    try:
-        return float(fields["traffic_bytes_per_launch_" + storage])
-    except (KeyError, ValueError):
-        return None
+    committed counter summary of this workload, or None if there is none or
+    it was taken on other kernel sources."""
+    for path in TRAFFIC_PROFILES:
+        try:
+            text = open(path).read()
+        except OSError:
+            continue
+        fields = dict(re.findall(r"^(\w+)\s*=\s*(\S+)\s*$", text, flags=re.M))
+        if fields.get("workload") != workload:
+            continue
+        if fields.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        try:
+            return float(fields["traffic_bytes_per_launch_" + storage])
+        except (KeyError, ValueError):
+            return None
+    return None
 
 
 def log(*a):

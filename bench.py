@@ -465,8 +465,8 @@ def main() -> int:
                          "line each: forward projector, FDK filter, learned-filter layers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the back-projector has no multi-GPU path in this "
-              "build (a z-slab split needs no exchange; see the design notes). Use --gpus 1.",
+        print("bench.py measures one GPU: the back-projector runs on one GPU per call "
+              "(a volume split into z-slabs needs no exchange between GPUs). Use --gpus 1.",
               file=sys.stderr)
         return 2
     if args.ops:

@@ -22,8 +22,7 @@
  * pixel that does not exist (outside [0,nh-1] x [0,nw-1]) is absent from the
  * sum, i.e. contributes zero.
  *
- * Readings of what the paper leaves open (the repository's design notes list
- * them as R1..R20):
+ * Readings of what the paper leaves open:
  *   - P_s maps world millimetres (voxel centres) to homogeneous pixel
  *     coordinates; voxel (i,j,k) has its centre at
  *     ((i-(nx-1)/2) dx + cx, (j-(ny-1)/2) dy + cy, (k-(nz-1)/2) dz + cz);

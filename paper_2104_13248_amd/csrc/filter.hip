@@ -374,7 +374,8 @@ __global__ __launch_bounds__(fft_threads<M>()) void filter_fft_kernel(const Filt
     constexpr int T = fft_threads<M>();
     // inverse transform as conj(FFT(conj(Z H))) (H is real and holds 1/M);
     // its last pass writes row a = Re, row b = -Im of the first nw outputs
-    // straight to the stack
+    // straight to the stack.  conj_zh reads conj(Z H) for a separate first
+    // inverse pass (M = 16); longer transforms apply H in fft_middle.
     auto conj_zh = [&](int k) {
         const float2 z = buf[fpad(k)];
         const float h = H[k];

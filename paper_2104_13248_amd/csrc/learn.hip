@@ -356,7 +356,9 @@ __device__ __forceinline__ lds_void_t* lds_ptr(const void* p)
     return (lds_void_t*)(size_t)(unsigned)(size_t)(__attribute__((address_space(3))) const char*)p;
 }
 
-__global__ __launch_bounds__(256) void conv32_mfma_kernel(const float* __restrict__ in,
+// Four blocks per CU (their LDS fits four times in 160 KB): at most 128
+// registers per lane.
+__global__ __launch_bounds__(256, 4) void conv32_mfma_kernel(const float* __restrict__ in,
                                                         const float* __restrict__ wa,
                                                         const float* __restrict__ bias,
                                                         const float* __restrict__ mask,
@@ -419,26 +421,48 @@ __global__ __launch_bounds__(256) void conv32_mfma_kernel(const float* __restric
             }
         }
     }
-    // D: lane l, register q -> channel ot*16 + 4 (l/16) + q, position l%16 of the tile
+    // D: lane l, register q -> channel ot*16 + 4 (l/16) + q, position l%16 of
+    // the tile.  Per o-tile, the bias, mask and addend of its 16 outputs are
+    // loaded before any is used (one wait instead of one per output);
+    // positions past the row load from its last position and are not stored.
+    const int xl = x0 + wave * 64 + (lane & 15);
+    const size_t rb = ((size_t)r * 32 + 4 * (lane >> 4)) * len;       // channel 4 (l/16)
+    int xc[4];
 #pragma unroll
-    for (int ot = 0; ot < 2; ++ot)
+    for (int xt = 0; xt < 4; ++xt) xc[xt] = min(xl + 16 * xt, len - 1);
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+        const size_t ro = rb + (size_t)(ot * 16) * len;
+        float bs[4], mk[4][4], ad[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bs[q] = bias ? bias[ot * 16 + 4 * (lane >> 4) + q] : 0.f;
+        if (mask) {
+#pragma unroll
+            for (int xt = 0; xt < 4; ++xt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) mk[xt][q] = mask[ro + (size_t)q * len + xc[xt]];
+        }
+        if (add) {
+#pragma unroll
+            for (int xt = 0; xt < 4; ++xt)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ad[xt][q] = add[ro + (size_t)q * len + xc[xt]];
+        }
 #pragma unroll
         for (int xt = 0; xt < 4; ++xt) {
-            const int x = x0 + wave * 64 + 16 * xt + (lane & 15);
-            if (x < len) {
+            if (xl + 16 * xt < len) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int o = ot * 16 + 4 * (lane >> 4) + q;
-                    const size_t oc = ((size_t)r * 32 + o) * len + x;
-                    float y = acc[ot][xt][q] + (bias ? bias[o] : 0.f);
+                    float y = acc[ot][xt][q] + bs[q];
                     if (relu) y = fmaxf(y, 0.f);
-                    if (mask && !(mask[oc] > 0.f)) y = 0.f;
+                    if (mask && !(mk[xt][q] > 0.f)) y = 0.f;
                     y *= alpha;
-                    if (add) y += add[oc];
-                    out[oc] = y;
+                    if (add) y += ad[xt][q];
+                    out[ro + (size_t)q * len + xl + 16 * xt] = y;
                 }
             }
         }
+    }
 }
 
 // grad_w[o][i][t] += sum_{r,x} gout[r][o][x] in[r][i][x + t - k/2]

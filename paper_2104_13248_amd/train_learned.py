@@ -105,6 +105,16 @@ def timed_reconstruction(f: LearnedFilter, data: Data, raw: torch.Tensor, reps: 
     return out
 
 
+def learning_rate(a, it: int, total: int) -> float:
+    """Rate of step it of total.  Cosine decay to zero (the default) lets the
+    final parameters, which are the ones evaluated, settle: at a constant rate
+    the single-phantom steps leave them wherever the last noisy updates put
+    them."""
+    if a.schedule == "constant":
+        return a.lr
+    return a.lr * 0.5 * (1.0 + math.cos(math.pi * it / max(total, 1)))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--phantoms", type=int, default=2000, help="training phantoms per epoch")
@@ -113,6 +123,8 @@ def main(argv=None):
     ap.add_argument("--target-views", type=int, default=720)
     ap.add_argument("--held-out", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--schedule", choices=("cosine", "constant"), default="cosine",
+                    help="learning rate over the run: cosine decay from --lr to 0, or constant")
     ap.add_argument("--replace", action="store_true",
                     help="network replaces the ramp filter instead of correcting it")
     ap.add_argument("--scale", type=int, default=1,
@@ -154,7 +166,7 @@ def main(argv=None):
     loss_acc = torch.zeros(1, device=dev)
     for it in range(start, total):
         raw, tgt = data.pair(it % a.phantoms)
-        loss_acc += f.train_step(raw, tgt, data.scan, data.sparse, a.lr)
+        loss_acc += f.train_step(raw, tgt, data.scan, data.sparse, learning_rate(a, it, total))
         if (it + 1) % a.log_every == 0 or it + 1 == total:
             n = int(torch.tensor(cfg["shape"]).prod())
             mse = float(loss_acc) / (n * a.log_every)

@@ -275,3 +275,19 @@ def test_short_training_beats_ramp_on_held_out():
     e1 = held_err()
     log("held-out rel-L2 ramp %.4f learned %.4f" % (e0, e1))
     assert e1 < 0.95 * e0
+
+
+def test_training_driver_end_to_end():
+    """The training command at an eighth of C5's sampling (32^3, 64^2
+    detector, 12-view scans against 96-view targets): six steps with the
+    cosine learning-rate schedule, held-out evaluation before and after,
+    finite results, and the summary's bookkeeping."""
+    import math
+    from paper_2104_13248_amd import train_learned
+    s = train_learned.main(["--scale", "8", "--phantoms", "6", "--held-out", "2",
+                            "--views", "12", "--target-views", "96", "--log-every", "3"])
+    log("driver summary", {k: s[k] for k in ("ramp_rel_l2", "learned_rel_l2")})
+    assert s["steps"] == 6 and s["shape"] == [32, 32, 32] and s["detector"] == [64, 64]
+    assert s["ramp_rel_l2"] == s["ramp_rel_l2_before"] == s["learned_rel_l2_before"]
+    assert math.isfinite(s["learned_rel_l2"]) and 0.0 < s["learned_rel_l2"] < 2.0 * s["ramp_rel_l2"]
+    assert s["learned_ms"] > 0.0 and s["ramp_ms"] > 0.0
